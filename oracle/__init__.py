@@ -1,0 +1,379 @@
+"""FP64 CPU oracle for fisheye plane-sweep stereo -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never calls it; the two share no code.
+
+The arithmetic lives in ``psweep_oracle.c`` (plain C, double precision,
+OpenMP over pixels); this module only marshals arguments.  Every function
+cites the part of Cui et al. (Sec. III-A plane sweep and multi-scale strategy,
+Sec. III-C Eq. (1) camera model) it follows; the readings of points the paper
+leaves open are listed in the C source.
+
+Parity status: every function is pinned by the CPU tests in ``tests/`` except
+the level merge (``merge``), which is pinned only by construction checks
+(parity unpinned against the paper, which gives no merge rule).
+"""
+from __future__ import annotations
+
+import ctypes
+import functools
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_d = ctypes.c_double
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE double)."""
+    if force or not os.path.exists(_LIB_PATH):
+        src = os.path.join(_HERE, "psweep_oracle.c")
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+                               "-shared", "-fPIC", src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OrCamera(ctypes.Structure):
+    _fields_ = [("xi", _d), ("fx", _d), ("fy", _d), ("cx", _d), ("cy", _d),
+                ("width", _i32), ("height", _i32)]
+
+
+class OrPose(ctypes.Structure):
+    _fields_ = [("R", _d * 9), ("t", _d * 3)]
+
+
+class OrImage(ctypes.Structure):
+    _fields_ = [("width", _i32), ("height", _i32), ("data", ctypes.POINTER(_d))]
+
+
+class OrParams(ctypes.Structure):
+    _fields_ = [("n_fronto", _i32), ("near_m", _d), ("far_m", _d),
+                ("n_ground", _i32), ("h_lo", _d), ("h_hi", _d),
+                ("window", _i32), ("best_k", _i32), ("var_floor", _d),
+                ("ground_n", _d * 3), ("ground_d", _d), ("temperature", _d)]
+
+
+@functools.lru_cache(maxsize=1)
+def lib():
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    L = ctypes.CDLL(_LIB_PATH)
+    PC, PP, PI, PR = (ctypes.POINTER(OrCamera), ctypes.POINTER(OrPose), ctypes.POINTER(OrImage),
+                      ctypes.POINTER(OrParams))
+    L.or_unproject.argtypes = [PC, _d, _d, _p]
+    L.or_unproject.restype = ctypes.c_int
+    L.or_project.argtypes = [PC, _p, _p, _p]
+    L.or_project.restype = ctypes.c_int
+    L.or_parabola.argtypes = [_d, _d, _d]
+    L.or_parabola.restype = _d
+    L.or_plane_param.argtypes = [PR, ctypes.c_int, _p]
+    L.or_plane_param.restype = _d
+    L.or_warp.argtypes = [PR, PC, PC, PP, ctypes.c_int, _d, _d, _p, _p, _p]
+    L.or_warp.restype = ctypes.c_int
+    L.or_sweep.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i64, _p] + [_p] * 10
+    L.or_sweep.restype = None
+    L.or_window_cost.argtypes = [PR, PC, PI, PC, PI, PP, _i32, _i32, _i32, _p]
+    L.or_window_cost.restype = None
+    L.or_downsample2.argtypes = [_p, _i32, _i32, _p]
+    L.or_downsample2.restype = None
+    L.or_level_camera.argtypes = [PC, _i32, _i32, _i32, _i32, _i32, PC]
+    L.or_level_camera.restype = None
+    L.or_merge.argtypes = [PC, PR, PR, _i32, _i32, _i32, _p, _p, _i32, _i32, _i32, _i32, _p, _p,
+                           _p, _p, _p, _p]
+    L.or_merge.restype = None
+    L.or_soft_forward.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i64, _p, _p, _p]
+    L.or_soft_forward.restype = None
+    L.or_soft_backward.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i32, _i32, _i32, _i32, _p, _p, _p]
+    L.or_soft_backward.restype = None
+    return L
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+def camera(c) -> OrCamera:
+    return OrCamera(float(c.xi), float(c.fx), float(c.fy), float(c.cx), float(c.cy),
+                    int(c.width), int(c.height))
+
+
+def pose(ps) -> OrPose:
+    o = OrPose()
+    o.R[:] = [float(v) for v in np.asarray(ps.R, np.float64).ravel()]
+    o.t[:] = [float(v) for v in np.asarray(ps.t, np.float64).ravel()]
+    return o
+
+
+class _Img:
+    """Keeps the float64 copy alive while the struct points at it."""
+
+    def __init__(self, arr):
+        self.arr = np.ascontiguousarray(np.asarray(arr, dtype=np.float64))
+        self.s = OrImage(self.arr.shape[1], self.arr.shape[0], self.arr.ctypes.data_as(ctypes.POINTER(_d)))
+
+
+def params(level, settings) -> OrParams:
+    o = OrParams()
+    o.n_fronto, o.near_m, o.far_m = int(level.n_fronto), float(level.near), float(level.far)
+    o.n_ground, o.h_lo, o.h_hi = int(level.n_ground), float(level.h_lo), float(level.h_hi)
+    o.window, o.best_k, o.var_floor = int(level.window), int(settings.best_k), float(settings.var_floor)
+    o.ground_n[:] = [float(v) for v in settings.ground_n]
+    o.ground_d = float(settings.ground_d)
+    o.temperature = float(settings.temperature)
+    return o
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+# ----------------------------------------------------------------------------
+# camera model (Sec. III-C, Eq. (1))
+# ----------------------------------------------------------------------------
+def unproject(cam, u: float, v: float):
+    """Unit ray of pixel (u, v) by Eq. (1); None where it is undefined."""
+    r = np.zeros(3)
+    ok = lib().or_unproject(ctypes.byref(camera(cam)), float(u), float(v), r.ctypes.data)
+    return r if ok else None
+
+
+def project(cam, X):
+    """Unified-model projection (u, v) of a camera-frame point; None if the
+    point is behind the model's viewpoint."""
+    X = np.ascontiguousarray(np.asarray(X, np.float64))
+    u, v = np.zeros(1), np.zeros(1)
+    ok = lib().or_project(ctypes.byref(camera(cam)), X.ctypes.data, u.ctypes.data, v.ctypes.data)
+    return (float(u[0]), float(v[0])) if ok else None
+
+
+def plane_param(level, settings, k: int):
+    """(parameter, step) of plane k: inverse depth for fronto planes, height
+    above the ground for ground planes (Sec. III-A)."""
+    st = np.zeros(1)
+    val = lib().or_plane_param(ctypes.byref(params(level, settings)), int(k), st.ctypes.data)
+    return float(val), float(st[0])
+
+
+def parabola(cm: float, c0: float, cp: float) -> float:
+    """Subpixel offset (plane steps) of the parabola through the costs of
+    the winner's two neighbours and the winner."""
+    return float(lib().or_parabola(float(cm), float(c0), float(cp)))
+
+
+def warp(level, settings, ref_cam, src_cam, ps, k: int, u: float, v: float):
+    """Position in the source of reference pixel (u, v) under plane k, and
+    the source-frame point; None if the plane is missed or the point does not
+    project (Sec. III-A: every plane position maps reference pixels into the
+    other images)."""
+    us, vs, X = np.zeros(1), np.zeros(1), np.zeros(3)
+    ok = lib().or_warp(ctypes.byref(params(level, settings)), ctypes.byref(camera(ref_cam)),
+                       ctypes.byref(camera(src_cam)), ctypes.byref(pose(ps)), int(k), float(u), float(v),
+                       us.ctypes.data, vs.ctypes.data, X.ctypes.data)
+    return (float(us[0]), float(vs[0]), X) if ok else None
+
+
+def window_cost(level, settings, ref_cam, ref_img, src_cam, src_img, ps, k, i, j):
+    """Dict with valid, zncc, cost (= (1 - ZNCC)/2, Sec. III-A) and the
+    window statistics of one (pixel, plane, source)."""
+    out = np.zeros(8)
+    R, S = _Img(ref_img), _Img(src_img)
+    lib().or_window_cost(ctypes.byref(params(level, settings)), ctypes.byref(camera(ref_cam)),
+                         ctypes.byref(R.s), ctypes.byref(camera(src_cam)), ctypes.byref(S.s),
+                         ctypes.byref(pose(ps)), int(k), int(i), int(j), out.ctypes.data)
+    keys = ["valid", "zncc", "cost", "mean_a", "mean_b", "s_aa", "s_bb", "s_ab"]
+    d = dict(zip(keys, out.tolist()))
+    d["valid"] = bool(d["valid"])
+    return d
+
+
+# ----------------------------------------------------------------------------
+# one level
+# ----------------------------------------------------------------------------
+def sweep_level(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, pixels=None,
+                volume: bool = False, srcvol: bool = False):
+    """Winner-take-all plane sweep of one level (Sec. III-A).
+
+    pixels: None (every pixel) or an int array [n, 2] of (x, y).
+    Returns a dict of per-pixel arrays (shape [H, W] for all pixels, [n]
+    otherwise): depth (range), z, index, delta, cost1, cost2, cost2_nonadj,
+    param (refined plane parameter), optionally volume [.., P] and
+    srcvol [.., P, S]."""
+    H, W = ref_img.shape
+    if pixels is None:
+        n, pix, shape = H * W, None, (H, W)
+    else:
+        pix = np.ascontiguousarray(np.asarray(pixels, np.int32).reshape(-1, 2))
+        n, shape = pix.shape[0], (pix.shape[0],)
+    P = level.n_fronto + level.n_ground
+    S = len(src_imgs)
+    out = {k: np.empty(n, np.float64) for k in ("depth", "z", "delta", "cost1", "cost2", "cost2_nonadj", "param")}
+    out["index"] = np.empty(n, np.int32)
+    vol = np.empty((n, P), np.float64) if volume else None
+    svol = np.empty((n, P, S), np.float64) if srcvol else None
+    R = _Img(ref_img)
+    Ss = [_Img(s) for s in src_imgs]
+    sarr = (OrImage * S)(*[s.s for s in Ss])
+    carr = (OrCamera * S)(*[camera(c) for c in src_cams])
+    parr = (OrPose * S)(*[pose(p) for p in poses])
+    lib().or_sweep(ctypes.byref(params(level, settings)), ctypes.byref(camera(ref_cam)), ctypes.byref(R.s), S,
+                   carr, sarr, parr, n, _ptr(pix),
+                   out["depth"].ctypes.data, out["z"].ctypes.data, out["index"].ctypes.data,
+                   out["delta"].ctypes.data, out["cost1"].ctypes.data, out["cost2"].ctypes.data,
+                   out["cost2_nonadj"].ctypes.data, out["param"].ctypes.data, _ptr(vol), _ptr(svol))
+    res = {k: v.reshape(shape) for k, v in out.items()}
+    if volume:
+        res["volume"] = vol.reshape(shape + (P,))
+    if srcvol:
+        res["srcvol"] = svol.reshape(shape + (P, S))
+    return res
+
+
+# ----------------------------------------------------------------------------
+# resolution levels (Sec. III-A, multi-scale strategy)
+# ----------------------------------------------------------------------------
+def downsample2(img: np.ndarray) -> np.ndarray:
+    """2x2 box filter, (s00 + s01 + s10 + s11 + 2) >> 2."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    out = np.empty((H // 2, W // 2), np.uint8)
+    lib().or_downsample2(img.ctypes.data, W, H, out.ctypes.data)
+    return out
+
+
+def level_camera(cam, downsample: int, crop=(0, 0, 0, 0)):
+    """Intrinsics of a level (downsampled and/or cropped view of `cam`)."""
+    from scenegen import Camera
+    o = OrCamera()
+    lib().or_level_camera(ctypes.byref(camera(cam)), int(downsample), int(crop[0]), int(crop[1]),
+                          int(crop[2]), int(crop[3]), ctypes.byref(o))
+    return Camera(o.xi, o.fx, o.fy, o.cx, o.cy, o.width, o.height)
+
+
+def level_inputs(frame, level):
+    """Reference image/camera and source images/cameras of one level: the
+    downsampled level shrinks every image; a crop cuts only the reference."""
+    ref, srcs = frame.ref, list(frame.srcs)
+    if level.downsample == 2:
+        ref = downsample2(ref)
+        srcs = [downsample2(s) for s in srcs]
+    ref_cam = level_camera(frame.ref_cam, level.downsample, level.crop)
+    src_cams = [level_camera(c, level.downsample) for c in frame.src_cams]
+    if level.crop[2] > 0:
+        x, y, w, h = level.crop
+        ref = np.ascontiguousarray(ref[y:y + h, x:x + w])
+    return ref_cam, ref, src_cams, srcs
+
+
+def merge(frame, settings, low, crop):
+    """Fuse the level results into full-resolution maps (reading of the
+    paper's up-sample-and-fuse step; parity unpinned against the paper)."""
+    full = frame.ref_cam
+    H, W = full.height, full.width
+    l0 = settings.levels[0]
+    l1 = settings.levels[1] if len(settings.levels) > 1 else None
+    depth, z = np.empty(H * W), np.empty(H * W)
+    lev = np.empty(H * W, np.uint8)
+    src = np.empty(H * W, np.int64)
+    lp = np.ascontiguousarray(low["param"].ravel())
+    li = np.ascontiguousarray(low["index"].ravel().astype(np.int32))
+    p0 = params(l0, settings)
+    if l1 is not None:
+        cp = np.ascontiguousarray(crop["param"].ravel())
+        ci = np.ascontiguousarray(crop["index"].ravel().astype(np.int32))
+        p1 = ctypes.byref(params(l1, settings))
+        cx, cy, cw, ch = l1.crop
+    else:
+        cp = ci = None
+        p1 = None
+        cx = cy = cw = ch = 0
+    lh, lw = low["index"].shape
+    lib().or_merge(ctypes.byref(camera(full)), ctypes.byref(p0), p1, int(l0.downsample), lw, lh,
+                   lp.ctypes.data, li.ctypes.data, cx, cy, cw, ch, _ptr(cp), _ptr(ci),
+                   depth.ctypes.data, z.ctypes.data, lev.ctypes.data, src.ctypes.data)
+    out = {"depth": depth.reshape(H, W), "z": z.reshape(H, W), "level": lev.reshape(H, W)}
+    for key in ("index", "delta", "cost1", "cost2"):
+        a = np.empty(H * W, low[key].dtype)
+        lv = low[key].ravel()
+        cv = crop[key].ravel() if l1 is not None else None
+        fill = -1 if key == "index" else (0.0 if key == "delta" else np.inf)
+        a[:] = fill
+        m0, m1 = lev == 0, lev == 1
+        a[m0] = lv[src[m0]]
+        if l1 is not None:
+            a[m1] = cv[src[m1]]
+        out[key] = a.reshape(H, W)
+    return out
+
+
+def run(frame, settings, pixels=None):
+    """Whole method on one frame: every level, then (with two levels, or a
+    downsampled level) the merge to full resolution.  With pixels given only a
+    single full-resolution level is supported (sampled parity checks)."""
+    levels = settings.levels
+    if pixels is not None:
+        assert len(levels) == 1 and levels[0].downsample == 1 and levels[0].crop[2] == 0
+    res = []
+    for lv in levels:
+        rc, ref, scs, srcs = level_inputs(frame, lv)
+        res.append(sweep_level(lv, settings, rc, ref, scs, srcs, frame.poses, pixels=pixels))
+    if len(levels) == 1 and levels[0].downsample == 1 and levels[0].crop[2] == 0:
+        out = dict(res[0])
+        if pixels is None:
+            out["level"] = np.where(res[0]["index"] >= 0, 0, 255).astype(np.uint8)
+        return {"merged": out, "levels": res}
+    merged = merge(frame, settings, res[0], res[1] if len(res) > 1 else None)
+    return {"merged": merged, "levels": res}
+
+
+# ----------------------------------------------------------------------------
+# soft-argmin forward and analytic gradient
+# ----------------------------------------------------------------------------
+def _src_arrays(src_cams, src_imgs, poses):
+    S = len(src_imgs)
+    Ss = [_Img(s) for s in src_imgs]
+    return (Ss, (OrImage * S)(*[s.s for s in Ss]), (OrCamera * S)(*[camera(c) for c in src_cams]),
+            (OrPose * S)(*[pose(p) for p in poses]))
+
+
+def soft_forward(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, pixels=None):
+    """Soft-argmin inverse depth rho_hat and logsumexp per pixel."""
+    H, W = ref_img.shape
+    if pixels is None:
+        n, pix, shape = H * W, None, (H, W)
+    else:
+        pix = np.ascontiguousarray(np.asarray(pixels, np.int32).reshape(-1, 2))
+        n, shape = pix.shape[0], (pix.shape[0],)
+    rh, lse = np.empty(n), np.empty(n)
+    R = _Img(ref_img)
+    keep, sarr, carr, parr = _src_arrays(src_cams, src_imgs, poses)
+    lib().or_soft_forward(ctypes.byref(params(level, settings)), ctypes.byref(camera(ref_cam)), ctypes.byref(R.s),
+                          len(src_imgs), carr, sarr, parr, n, _ptr(pix), rh.ctypes.data, lse.ctypes.data)
+    del keep
+    return rh.reshape(shape), lse.reshape(shape)
+
+
+def soft_backward(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, rect, grad):
+    """Analytic FP64 gradient of sum(grad * rho_hat) over rect = (x0, y0, w, h)
+    with respect to the source images and the se(3) left perturbation (v,
+    omega) of every source pose.  Returns (list of [H_s, W_s], [S, 6])."""
+    x0, y0, w, h = [int(v) for v in rect]
+    g = np.ascontiguousarray(np.asarray(grad, np.float64).reshape(h, w))
+    R = _Img(ref_img)
+    keep, sarr, carr, parr = _src_arrays(src_cams, src_imgs, poses)
+    gs = [np.zeros(np.asarray(s).shape, np.float64) for s in src_imgs]
+    gptrs = (ctypes.c_void_p * len(gs))(*[a.ctypes.data for a in gs])
+    gp = np.zeros(6 * len(src_imgs))
+    lib().or_soft_backward(ctypes.byref(params(level, settings)), ctypes.byref(camera(ref_cam)),
+                           ctypes.byref(R.s), len(src_imgs), carr, sarr, parr, x0, y0, w, h,
+                           g.ctypes.data, gptrs, gp.ctypes.data)
+    del keep
+    return gs, gp.reshape(-1, 6)
