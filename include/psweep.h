@@ -1,0 +1,239 @@
+/*
+ * psweep.h -- C ABI of the MI355X (gfx950) fisheye plane-sweep stereo library.
+ *
+ * The library computes, for a reference fisheye image and up to four
+ * supporting fisheye images with known relative poses, a depth map of the
+ * reference view by plane-sweeping stereo (Cui et al., "Real-Time Dense
+ * Mapping for Self-Driving Vehicles using Fisheye Cameras", Sec. III-A):
+ *   - planes parallel to the reference image plane and planes parallel to the
+ *     ground plane given by the extrinsic calibration (Sec. III-A);
+ *   - every reference pixel's ray (unified camera model, Eq. (1), Sec. III-C)
+ *     is intersected with each plane, projected into each source through the
+ *     same model and bilinearly sampled;
+ *   - the matching cost is negative ZNCC over a window, cost = (1 - ZNCC) / 2,
+ *     so ZNCC -1 costs 1 and ZNCC +1 costs 0 (Sec. III-A);
+ *   - the best plane per pixel with its first and second best costs (Sec.
+ *     III-A, depth-map filtering), refined by a parabola through the winner
+ *     and its two neighbours;
+ *   - two resolution levels: a downsampled full field of view and a
+ *     full-resolution centre crop, fused into one full-resolution map (Sec.
+ *     III-A, multi-scale strategy);
+ *   - optionally a soft-argmin over the fronto planes with a gradient with
+ *     respect to the source images and the source poses.
+ *
+ * Conventions shared by every call:
+ *   - Pixel (i, j) has its centre at (u, v) = (i, j); normalized coordinates
+ *     are x = (u - cx) / fx, y = (v - cy) / fy.
+ *   - Reference frame: x right, y down, z forward, metres.  A source sees
+ *     X_src = R X_ref + t (R row-major).
+ *   - Images are 8-bit grey, row-major, in device memory, with a row pitch in
+ *     bytes.  Output maps are row-major device arrays with a pitch in
+ *     elements.
+ *   - All device memory (images, outputs, workspace) is owned by the caller.
+ *     The context owns host-side state only.
+ *   - Every call returns a psweep_status and never aborts.  Launch errors are
+ *     reported as PSWEEP_EHIP by the same or the next call.  Outputs are
+ *     undefined after an error.  psweep_last_error() gives a message.
+ *   - Work is enqueued asynchronously on the caller's HIP stream; only
+ *     psweep_destroy() synchronises.  A context must not be used from two
+ *     host threads at once.
+ *   - Invalid pixels are marked in-band: depth and z NaN, index -1, delta 0,
+ *     cost1 and cost2 +inf, level 255.
+ */
+#ifndef PSWEEP_H
+#define PSWEEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSWEEP_MAX_SOURCES 4
+#define PSWEEP_MAX_LEVELS 2
+#define PSWEEP_MAX_PLANES 1024   /* fronto + ground planes per level */
+
+typedef enum {
+    PSWEEP_OK = 0,
+    PSWEEP_EINVAL = -1,        /* bad argument: NULL, size, range, layout */
+    PSWEEP_ESTATE = -2,        /* call out of order */
+    PSWEEP_ENOMEM = -3,        /* host allocation failed or workspace too small */
+    PSWEEP_EHIP = -4,          /* HIP runtime or launch error */
+    PSWEEP_EUNSUPPORTED = -5   /* valid request this build does not implement */
+} psweep_status;
+
+enum { PSWEEP_STORAGE_F32 = 0, PSWEEP_STORAGE_F16 = 1, PSWEEP_STORAGE_BF16 = 2 };
+enum { PSWEEP_MODE_WTA = 0, PSWEEP_MODE_SOFT = 1 };
+enum { PSWEEP_LAUNCH_GRID = 0, PSWEEP_LAUNCH_PERSISTENT = 1 };
+
+typedef struct psweep_ctx psweep_ctx;
+
+/* Unified (Mei) fisheye camera, Sec. III-C Eq. (1): mirror parameter xi in
+ * [0, 1] plus a pinhole part; no lens distortion. */
+typedef struct {
+    double xi, fx, fy, cx, cy;
+    int32_t width, height;
+} psweep_camera;
+
+/* Rigid transform reference -> source: X_src = R X_ref + t (Sec. III-A,
+ * "known relative poses"). */
+typedef struct {
+    double R[9];
+    double t[3];
+} psweep_pose;
+
+/* One resolution level (Sec. III-A).  Fronto planes are uniform in inverse
+ * depth from far_m (index 0) to near_m; ground-parallel planes follow,
+ * uniform in height above the ground from h_lo to h_hi.  downsample 2 halves
+ * every image with a 2x2 box filter (rounded integer mean).  A crop (crop_w >
+ * 0) restricts the reference to a rectangle of the (possibly downsampled)
+ * reference image; the sources stay whole. */
+typedef struct {
+    int32_t n_fronto;
+    double near_m, far_m;
+    int32_t n_ground;
+    double h_lo, h_hi;
+    int32_t window;                 /* odd, 3..15 */
+    int32_t downsample;             /* 1 or 2 */
+    int32_t crop_x, crop_y, crop_w, crop_h;
+} psweep_level;
+
+typedef struct {
+    int32_t n_levels;               /* 1 or 2 (level 1 is the crop level) */
+    psweep_level level[PSWEEP_MAX_LEVELS];
+    double ground_n[3], ground_d;   /* ground plane n . X = ground_d, unit n, reference frame */
+    int32_t best_k;                 /* per plane, mean of the best_k valid source costs */
+    double var_floor;               /* windows with variance <= var_floor (grey^2) are unusable */
+    int32_t storage;                /* PSWEEP_STORAGE_*: precision of staged warped samples */
+    int32_t mode;                   /* PSWEEP_MODE_WTA or PSWEEP_MODE_SOFT */
+    double temperature;             /* soft mode: softmax over -cost / temperature */
+    int32_t launch;                 /* PSWEEP_LAUNCH_GRID or PSWEEP_LAUNCH_PERSISTENT */
+    int32_t max_width, max_height;  /* largest reference / source image */
+    int32_t max_sources;            /* <= PSWEEP_MAX_SOURCES */
+    int32_t max_frames;             /* frames per psweep_run */
+    int32_t max_camera_sets;
+} psweep_config;
+
+/* One frame set: device images and the camera set describing them. */
+typedef struct {
+    const uint8_t *ref;
+    int64_t ref_pitch;
+    const uint8_t *src[PSWEEP_MAX_SOURCES];
+    int64_t src_pitch[PSWEEP_MAX_SOURCES];
+    int32_t camera_set;
+} psweep_frame;
+
+/* Per-pixel maps; any pointer may be NULL (not written).  pitch in elements,
+ * 0 = the map's width. */
+typedef struct {
+    float *depth;       /* range along the unit ray, metres */
+    float *z;           /* camera-frame z, metres */
+    int32_t *index;     /* winning plane of the level the pixel came from */
+    float *delta;       /* parabolic subpixel offset, plane steps, [-0.5, 0.5] */
+    float *cost1;       /* best aggregated cost */
+    float *cost2;       /* best aggregated cost over all other planes */
+    uint8_t *level;     /* merged maps only: 0 low level, 1 crop level, 255 invalid */
+    int64_t pitch;
+} psweep_maps;
+
+typedef struct {
+    psweep_maps merged;                       /* full reference resolution */
+    psweep_maps level[PSWEEP_MAX_LEVELS];     /* per level, at the level's size (optional) */
+    float *soft_invdepth;                     /* soft mode, full resolution */
+    float *soft_lse;                          /* soft mode: log-sum-exp of -cost / T */
+    int64_t soft_pitch;
+} psweep_output;
+
+/* Create a context for `cfg`.  EINVAL on inconsistent settings (even window,
+ * fewer than 2 planes in a used family, non-positive plane distances, sizes
+ * or counts out of range, best_k outside [1, max_sources]); EUNSUPPORTED for
+ * soft mode with ground planes, with two levels, with a downsampled or
+ * cropped level or with the persistent launch.  *out receives the context. */
+psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out);
+
+/* Bytes of device workspace the context needs (fixed by the config). */
+psweep_status psweep_workspace_size(const psweep_ctx *ctx, size_t *bytes);
+
+/* Bind caller-allocated device memory (>= psweep_workspace_size bytes,
+ * 256-byte aligned).  ENOMEM if smaller, EINVAL if misaligned or NULL. */
+psweep_status psweep_set_workspace(psweep_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Define camera set `camera_set` (0 .. max_camera_sets-1): the reference
+ * camera, n_src source cameras and the n_src poses reference -> source.
+ * Sizes must not exceed max_width x max_height; n_src in [1, max_sources];
+ * xi in [0, 1]; fx, fy > 0; R orthonormal to 1e-6.  Host pointers, copied. */
+psweep_status psweep_set_cameras(psweep_ctx *ctx, int32_t camera_set, const psweep_camera *ref,
+                                 int32_t n_src, const psweep_camera *src, const psweep_pose *ref_to_src);
+
+/* Override the crop rectangle of level 1 for one camera set (frames of mixed
+ * sizes need their own crop).  Full-resolution pixels of the reference. */
+psweep_status psweep_set_crop(psweep_ctx *ctx, int32_t camera_set, int32_t x, int32_t y, int32_t w,
+                              int32_t h);
+
+/* Sweep n_frames frame sets (1 .. max_frames) and write out[i] for frames[i].
+ * `frames` and `out` are host arrays of device pointers.  Enqueued on
+ * hip_stream (a hipStream_t; NULL = default stream).  ESTATE before
+ * psweep_set_workspace or for a camera set never defined; EINVAL for NULL
+ * images, pitches below the width, or maps whose pitch is below their width.
+ * Soft mode requires n_frames == 1.  The images must stay alive and unchanged
+ * until a following psweep_soft_depth_backward has run. */
+psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                         const psweep_output *out, void *hip_stream);
+
+/* Gradient of L = sum_p g_p * soft_invdepth_p (g = d_grad_invdepth, full
+ * resolution, pitch soft_pitch of the last run) with respect to every source
+ * image (d_grad_src[s]: float device array of the source's size, row-major,
+ * overwritten) and to every source pose as a left perturbation X_src ->
+ * X_src + v + omega x X_src (d_grad_pose: device doubles [n_src][6] ordered
+ * v, omega; overwritten).  Uses the images and soft outputs of the last
+ * psweep_run, which must have been a soft run (ESTATE otherwise).  Warps are
+ * recomputed, not stored.  Image gradients are accumulated with atomics, so
+ * they vary in the last bits from run to run. */
+psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_invdepth,
+                                         float *const *d_grad_src, double *d_grad_pose, void *hip_stream);
+
+/* Tile shape of the sweep kernel for one level: rows per wave (8 or 16)
+ * and waves per workgroup (2 or 4); 0 restores the default.  Used by the
+ * autotuner.  EINVAL for other values. */
+psweep_status psweep_set_tile(psweep_ctx *ctx, int32_t level, int32_t rows_per_wave, int32_t waves);
+
+/* Capture one psweep_run of these frames into a HIP graph owned by the
+ * context (replacing any earlier graph).  The frame and output pointers are
+ * baked in.  Capture happens on hip_stream, which must not be capturing. */
+psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                                   const psweep_output *out, void *hip_stream);
+
+/* Launch the captured graph on hip_stream.  ESTATE if none was captured. */
+psweep_status psweep_graph_launch(psweep_ctx *ctx, void *hip_stream);
+
+/* Record HIP events around every sweep-kernel launch of later runs (on = 1)
+ * or stop (on = 0).  Off by default: events are outside the timed work. */
+psweep_status psweep_set_timing(psweep_ctx *ctx, int32_t on);
+
+/* Average duration in milliseconds of the sweep kernel launches enqueued by
+ * the last psweep_run (measured with HIP events on the launch stream, read
+ * after the stream has been synchronised by the caller).  ESTATE if no run
+ * recorded events. */
+psweep_status psweep_sweep_kernel_ms(psweep_ctx *ctx, double *ms, int32_t *n_launches);
+
+/* Plane-pixel evaluations (pixels x planes, all levels, all frames) of one
+ * psweep_run with these frames, for throughput accounting. */
+psweep_status psweep_plane_pixels(const psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                                  int64_t *count);
+
+/* Wait for the context's work, free its host state and events. */
+void psweep_destroy(psweep_ctx *ctx);
+
+/* Message of the last error on this context (or of the last failed create
+ * when ctx is NULL); never NULL. */
+const char *psweep_last_error(const psweep_ctx *ctx);
+
+/* Library version string. */
+const char *psweep_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSWEEP_H */

@@ -1,0 +1,846 @@
+// Host side of the psweep C ABI (include/psweep.h): argument checks, the
+// workspace layout, FP64 level cameras, the per-run job tables and the launch
+// sequence
+//   table upload -> FP64 plane setup -> level images -> border marks ->
+//   sweep (one grid per level, or one persistent launch) -> level merge.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/psweep.h"
+#include "psweep_internal.h"
+
+using namespace psw;
+
+extern "C" const void *psw_setup_kernel();
+extern "C" const void *psw_prep_kernel();
+extern "C" const void *psw_border_kernel();
+extern "C" const void *psw_reset_kernel();
+extern "C" const void *psw_merge_kernel();
+extern "C" const void *psw_backward_kernel(int win, int n_src);
+extern "C" size_t psw_backward_lds(int win, int n_src);
+extern "C" const void *psw_zero_kernel();
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+thread_local std::string g_create_error;
+
+struct CamSet {
+    bool defined = false;
+    psweep_camera ref{};
+    int n_src = 0;
+    psweep_camera src[PSWEEP_MAX_SOURCES]{};
+    psweep_pose pose[PSWEEP_MAX_SOURCES]{};
+    bool crop_set = false;
+    int crop[4] = {0, 0, 0, 0};
+};
+
+struct LevelCam {
+    double xi, fx, fy, cx, cy;
+    int w, h;
+};
+
+// intrinsics of a level: 2x2 downsampling puts a level pixel's centre at the
+// centre of its 2x2 block (2 i + 0.5); a crop shifts the principal point
+LevelCam level_cam(const psweep_camera &c, int ds, int cx0, int cy0, int cw, int ch) {
+    LevelCam o{c.xi, c.fx, c.fy, c.cx, c.cy, c.width, c.height};
+    if (ds == 2) {
+        o.fx = c.fx / 2.0; o.fy = c.fy / 2.0;
+        o.cx = (c.cx - 0.5) / 2.0; o.cy = (c.cy - 0.5) / 2.0;
+        o.w = c.width / 2; o.h = c.height / 2;
+    }
+    if (cw > 0) {
+        o.cx -= cx0; o.cy -= cy0;
+        o.w = cw; o.h = ch;
+    }
+    return o;
+}
+
+const KernelEntry *g_entries = nullptr;
+int g_n_entries = 0;
+std::vector<KernelEntry> g_all;
+
+void load_tables() {
+    if (!g_all.empty()) return;
+    const KernelEntry *t;
+    int n = psw_kernels_grid(&t);
+    g_all.insert(g_all.end(), t, t + n);
+    n = psw_kernels_extra(&t);
+    g_all.insert(g_all.end(), t, t + n);
+    n = psw_kernels_persistent(&t);
+    g_all.insert(g_all.end(), t, t + n);
+    g_entries = g_all.data();
+    g_n_entries = (int)g_all.size();
+}
+
+const KernelEntry *find_kernel(int win, int rows, int waves, int n_src, int store, int soft, int persistent) {
+    load_tables();
+    for (int i = 0; i < g_n_entries; ++i) {
+        const KernelEntry &e = g_entries[i];
+        if (e.persistent == persistent && e.rows == rows && e.waves == waves && e.n_src == n_src &&
+            e.store == store && e.soft == soft && (persistent || e.win == win))
+            return &e;
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+struct psweep_ctx {
+    psweep_config cfg{};
+    std::vector<CamSet> sets;
+    int P[PSWEEP_MAX_LEVELS] = {0, 0};
+    // level size bounds for the workspace
+    int ref_w[PSWEEP_MAX_LEVELS] = {0, 0}, ref_h[PSWEEP_MAX_LEVELS] = {0, 0};
+    int src_w[PSWEEP_MAX_LEVELS] = {0, 0}, src_h[PSWEEP_MAX_LEVELS] = {0, 0};
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0, ws_need = 0;
+    size_t table_bytes = 0, off_table[2] = {0, 0}, off_counter[2] = {0, 0}, off_slots = 0, slot_bytes = 0;
+    size_t s_ref[PSWEEP_MAX_LEVELS], s_tex[PSWEEP_MAX_LEVELS], s_maps[PSWEEP_MAX_LEVELS], s_htab[PSWEEP_MAX_LEVELS],
+        s_theta[PSWEEP_MAX_LEVELS];
+    // pinned staging of the job tables (double buffered)
+    char *staging[2] = {nullptr, nullptr};
+    hipEvent_t staging_ev[2] = {nullptr, nullptr};
+    bool staging_pending[2] = {false, false};
+    int staging_idx = 0;
+    std::vector<char> last_table;
+    uint64_t cam_version = 1, setup_version = 0;
+    int tile_rows[PSWEEP_MAX_LEVELS] = {8, 8}, tile_waves[PSWEEP_MAX_LEVELS] = {4, 4};
+    // timing of sweep launches
+    bool timing = false;
+    std::vector<hipEvent_t> ev0, ev1;
+    int n_timed = 0;
+    // soft-mode state for the backward pass
+    bool soft_ready = false;
+    psweep_frame soft_frame{};
+    float *soft_rho = nullptr, *soft_lse = nullptr;
+    int64_t soft_pitch = 0;
+    size_t soft_job_off = 0;   // device address of the job used by the backward
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+psweep_status fail(psweep_ctx *c, psweep_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+psweep_status hip_fail(psweep_ctx *c, hipError_t e, const char *what) {
+    return fail(c, PSWEEP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PSW_HIP(call, what)                               \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+bool single_full(const psweep_config &c) {
+    return c.n_levels == 1 && c.level[0].downsample == 1 && c.level[0].crop_w == 0;
+}
+
+psweep_status check_config(const psweep_config *c) {
+    auto bad = [](const std::string &m) { return fail(nullptr, PSWEEP_EINVAL, m); };
+    if (c->n_levels < 1 || c->n_levels > PSWEEP_MAX_LEVELS) return bad("n_levels must be 1 or 2");
+    if (c->max_width < 8 || c->max_height < 8 || c->max_width > 8192 || c->max_height > 8192)
+        return bad("max_width/max_height out of [8, 8192]");
+    if (c->max_sources < 1 || c->max_sources > PSWEEP_MAX_SOURCES) return bad("max_sources out of [1, 4]");
+    if (c->max_frames < 1 || c->max_frames * c->n_levels > kMaxJobs) return bad("max_frames out of range");
+    if (c->max_camera_sets < 1 || c->max_camera_sets > 4096) return bad("max_camera_sets out of range");
+    if (c->best_k < 1 || c->best_k > c->max_sources) return bad("best_k out of [1, max_sources]");
+    if (!(c->var_floor >= 0.0)) return bad("var_floor must be >= 0");
+    if (c->storage < 0 || c->storage > 2) return bad("storage must be F32, F16 or BF16");
+    if (c->mode != PSWEEP_MODE_WTA && c->mode != PSWEEP_MODE_SOFT) return bad("mode must be WTA or SOFT");
+    if (c->launch != PSWEEP_LAUNCH_GRID && c->launch != PSWEEP_LAUNCH_PERSISTENT) return bad("bad launch kind");
+    const double gn = std::sqrt(c->ground_n[0] * c->ground_n[0] + c->ground_n[1] * c->ground_n[1] +
+                                c->ground_n[2] * c->ground_n[2]);
+    for (int l = 0; l < c->n_levels; ++l) {
+        const psweep_level &L = c->level[l];
+        if (L.window < 3 || L.window > 15 || (L.window & 1) == 0) return bad("window must be odd in [3, 15]");
+        if (L.downsample != 1 && L.downsample != 2) return bad("downsample must be 1 or 2");
+        if (L.n_fronto < 0 || L.n_ground < 0 || L.n_fronto + L.n_ground < 1 ||
+            L.n_fronto + L.n_ground > PSWEEP_MAX_PLANES)
+            return bad("plane counts out of range");
+        if (L.n_fronto == 1 || L.n_ground == 1) return bad("a used plane family needs >= 2 planes");
+        if (L.n_fronto > 0 && !(L.near_m > 0.0 && L.far_m > L.near_m)) return bad("need 0 < near_m < far_m");
+        if (L.n_ground > 0) {
+            if (!(L.h_hi > L.h_lo)) return bad("need h_lo < h_hi");
+            if (!(std::fabs(gn - 1.0) < 1e-6)) return bad("ground_n must be a unit vector");
+            if (!(c->ground_d - L.h_hi > 0.0)) return bad("ground planes must stay below the camera (ground_d > h_hi)");
+        }
+        if (L.crop_w < 0 || L.crop_h < 0 || (L.crop_w > 0 && (L.crop_x < 0 || L.crop_y < 0)))
+            return bad("bad crop rectangle");
+    }
+    if (c->n_levels == 2) {
+        if (c->level[0].crop_w != 0) return fail(nullptr, PSWEEP_EUNSUPPORTED, "level 0 must not be cropped");
+        if (c->level[1].downsample != 1) return fail(nullptr, PSWEEP_EUNSUPPORTED, "the crop level must be full resolution");
+        if (c->level[1].n_fronto < 1) return bad("the crop level needs fronto planes");
+    } else if (c->level[0].crop_w != 0) {
+        return fail(nullptr, PSWEEP_EUNSUPPORTED, "a single level cannot be cropped");
+    }
+    if (c->mode == PSWEEP_MODE_SOFT) {
+        if (!single_full(*c)) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode needs one full-resolution level");
+        if (c->level[0].n_ground != 0) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode sweeps fronto planes only");
+        if (c->launch != PSWEEP_LAUNCH_GRID) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode uses the grid launch");
+        if (c->storage != PSWEEP_STORAGE_F32) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode stages in FP32");
+        if (!(c->temperature > 0.0)) return bad("temperature must be > 0");
+    }
+    if (c->launch == PSWEEP_LAUNCH_PERSISTENT) {
+        for (int l = 0; l < c->n_levels; ++l)
+            if (c->level[l].window != 7 && c->level[l].window != 9)
+                return fail(nullptr, PSWEEP_EUNSUPPORTED, "the persistent launch supports windows 7 and 9");
+    }
+    return PSWEEP_OK;
+}
+
+struct Blob {
+    std::vector<char> bytes;
+    size_t jobs = 0, setups = 0, preps = 0, borders = 0, merges = 0;
+    int nj = 0, nm = 0;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *psweep_version(void) { return "psweep-gfx950 1.0"; }
+
+const char *psweep_last_error(const psweep_ctx *ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
+    if (!cfg || !out) return fail(nullptr, PSWEEP_EINVAL, "NULL argument");
+    *out = nullptr;
+    psweep_status st = check_config(cfg);
+    if (st != PSWEEP_OK) return st;
+    psweep_ctx *ctx = new (std::nothrow) psweep_ctx();
+    if (!ctx) return fail(nullptr, PSWEEP_ENOMEM, "host allocation failed");
+    ctx->cfg = *cfg;
+    ctx->sets.resize(cfg->max_camera_sets);
+    const int W = cfg->max_width, H = cfg->max_height;
+    for (int l = 0; l < cfg->n_levels; ++l) {
+        const psweep_level &L = cfg->level[l];
+        ctx->P[l] = L.n_fronto + L.n_ground;
+        ctx->src_w[l] = W / L.downsample;
+        ctx->src_h[l] = H / L.downsample;
+        ctx->ref_w[l] = ctx->src_w[l];
+        ctx->ref_h[l] = ctx->src_h[l];
+    }
+    // table region: every kind of record for kMaxJobs jobs
+    ctx->table_bytes = align_up(sizeof(JobDev) * kMaxJobs) + align_up(sizeof(SetupDev) * kMaxJobs) +
+                       align_up(sizeof(PrepDev) * kMaxJobs) + align_up(sizeof(BorderDev) * kMaxJobs) +
+                       align_up(sizeof(MergeDev) * kMaxJobs);
+    size_t off = 0;
+    for (int g = 0; g < 2; ++g) { ctx->off_table[g] = off; off += ctx->table_bytes; }
+    for (int g = 0; g < 2; ++g) { ctx->off_counter[g] = off; off += kAlign; }
+    ctx->off_slots = off;
+    size_t so = 0;
+    const int S = cfg->max_sources;
+    for (int l = 0; l < cfg->n_levels; ++l) {
+        const size_t rpx = (size_t)ctx->ref_w[l] * ctx->ref_h[l];
+        const size_t spx = (size_t)ctx->src_w[l] * ctx->src_h[l];
+        ctx->s_ref[l] = so;   so += align_up(rpx);
+        ctx->s_tex[l] = so;   so += align_up(spx * 4) * S;
+        ctx->s_maps[l] = so;  so += align_up(rpx * 4) * 4;
+        ctx->s_htab[l] = so;  so += align_up((size_t)ctx->P[l] * S * 9 * 4);
+        ctx->s_theta[l] = so; so += align_up((size_t)ctx->P[l] * 4);
+    }
+    ctx->slot_bytes = align_up(so);
+    ctx->ws_need = ctx->off_slots + ctx->slot_bytes * cfg->max_frames;
+    for (int b = 0; b < 2; ++b) {
+        if (hipHostMalloc((void **)&ctx->staging[b], ctx->table_bytes, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->staging_ev[b], hipEventDisableTiming) != hipSuccess) {
+            psweep_destroy(ctx);
+            return fail(nullptr, PSWEEP_EHIP, "pinned staging allocation failed");
+        }
+    }
+    load_tables();
+    // kernels with more than 64 KB of dynamic LDS need the limit raised
+    for (int i = 0; i < g_n_entries; ++i)
+        if (g_entries[i].lds > 65536)
+            (void)hipFuncSetAttribute(g_entries[i].fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g_entries[i].lds);
+    *out = ctx;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_workspace_size(const psweep_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return PSWEEP_EINVAL;
+    *bytes = ctx->ws_need;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_set_workspace(psweep_ctx *ctx, void *dev_ptr, size_t bytes) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (!dev_ptr) return fail(ctx, PSWEEP_EINVAL, "NULL workspace");
+    if (((uintptr_t)dev_ptr) % kAlign) return fail(ctx, PSWEEP_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < ctx->ws_need) return fail(ctx, PSWEEP_ENOMEM, "workspace smaller than psweep_workspace_size");
+    ctx->ws = (char *)dev_ptr;
+    ctx->ws_bytes = bytes;
+    ctx->last_table.clear();
+    ctx->setup_version = 0;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_set_cameras(psweep_ctx *ctx, int32_t camera_set, const psweep_camera *ref, int32_t n_src,
+                                 const psweep_camera *src, const psweep_pose *ref_to_src) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (camera_set < 0 || camera_set >= (int)ctx->sets.size()) return fail(ctx, PSWEEP_EINVAL, "camera_set out of range");
+    if (!ref || !src || !ref_to_src) return fail(ctx, PSWEEP_EINVAL, "NULL camera or pose");
+    if (n_src < 1 || n_src > ctx->cfg.max_sources) return fail(ctx, PSWEEP_EINVAL, "n_src out of [1, max_sources]");
+    if (ctx->cfg.best_k > n_src) return fail(ctx, PSWEEP_EINVAL, "best_k exceeds n_src");
+    auto cam_ok = [&](const psweep_camera &c) {
+        return c.xi >= 0.0 && c.xi <= 1.0 && c.fx > 0.0 && c.fy > 0.0 && c.width >= 8 && c.height >= 8 &&
+               c.width <= ctx->cfg.max_width && c.height <= ctx->cfg.max_height && std::isfinite(c.cx) &&
+               std::isfinite(c.cy);
+    };
+    if (!cam_ok(*ref)) return fail(ctx, PSWEEP_EINVAL, "bad reference camera (xi in [0,1], f > 0, size <= max)");
+    for (int s = 0; s < n_src; ++s) {
+        if (!cam_ok(src[s])) return fail(ctx, PSWEEP_EINVAL, "bad source camera");
+        const double *R = ref_to_src[s].R;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double d = 0;
+                for (int k = 0; k < 3; ++k) d += R[3 * a + k] * R[3 * b + k];
+                if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-6) return fail(ctx, PSWEEP_EINVAL, "R not orthonormal");
+            }
+    }
+    CamSet &cs = ctx->sets[camera_set];
+    cs.defined = true;
+    cs.ref = *ref;
+    cs.n_src = n_src;
+    for (int s = 0; s < n_src; ++s) { cs.src[s] = src[s]; cs.pose[s] = ref_to_src[s]; }
+    ctx->cam_version++;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_set_crop(psweep_ctx *ctx, int32_t camera_set, int32_t x, int32_t y, int32_t w, int32_t h) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (camera_set < 0 || camera_set >= (int)ctx->sets.size()) return fail(ctx, PSWEEP_EINVAL, "camera_set out of range");
+    if (ctx->cfg.n_levels != 2) return fail(ctx, PSWEEP_ESTATE, "only a two-level config has a crop level");
+    if (x < 0 || y < 0 || w < 8 || h < 8) return fail(ctx, PSWEEP_EINVAL, "bad crop rectangle");
+    CamSet &cs = ctx->sets[camera_set];
+    cs.crop_set = true;
+    cs.crop[0] = x; cs.crop[1] = y; cs.crop[2] = w; cs.crop[3] = h;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_set_tile(psweep_ctx *ctx, int32_t level, int32_t rows_per_wave, int32_t waves) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (level < 0 || level >= ctx->cfg.n_levels) return fail(ctx, PSWEEP_EINVAL, "level out of range");
+    if (rows_per_wave == 0 && waves == 0) { rows_per_wave = 8; waves = 4; }
+    if ((rows_per_wave != 8 && rows_per_wave != 16) || (waves != 2 && waves != 4))
+        return fail(ctx, PSWEEP_EINVAL, "rows_per_wave must be 8 or 16 and waves 2 or 4");
+    ctx->tile_rows[level] = rows_per_wave;
+    ctx->tile_waves[level] = waves;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_set_timing(psweep_ctx *ctx, int32_t on) {
+    if (!ctx) return PSWEEP_EINVAL;
+    ctx->timing = on != 0;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_plane_pixels(const psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames, int64_t *count) {
+    if (!ctx || !frames || !count || n_frames < 1) return PSWEEP_EINVAL;
+    int64_t n = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const int cs = frames[f].camera_set;
+        if (cs < 0 || cs >= (int)ctx->sets.size() || !ctx->sets[cs].defined) return PSWEEP_ESTATE;
+        const CamSet &C = ctx->sets[cs];
+        for (int l = 0; l < ctx->cfg.n_levels; ++l) {
+            const psweep_level &L = ctx->cfg.level[l];
+            int cw = L.crop_w, ch = L.crop_h;
+            if (l == 1 && C.crop_set) { cw = C.crop[2]; ch = C.crop[3]; }
+            const LevelCam lc = level_cam(C.ref, L.downsample, 0, 0, cw, ch);
+            n += (int64_t)lc.w * lc.h * (L.n_fronto + L.n_ground);
+        }
+    }
+    *count = n;
+    return PSWEEP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Build the per-run tables (host side) for `frames`, with device addresses
+// of the table region `tbase`.
+psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, const psweep_output *out,
+                           char *tbase, Blob &blob, std::vector<int> &job_frame) {
+    const psweep_config &cfg = ctx->cfg;
+    const int NL = cfg.n_levels;
+    const bool sf = single_full(cfg);
+    std::vector<JobDev> jobs;
+    std::vector<SetupDev> setups;
+    std::vector<PrepDev> preps;
+    std::vector<BorderDev> borders;
+    std::vector<MergeDev> merges;
+    int first_item = 0;
+    for (int f = 0; f < nf; ++f) {
+        const psweep_frame &fr = frames[f];
+        const int csi = fr.camera_set;
+        if (csi < 0 || csi >= (int)ctx->sets.size() || !ctx->sets[csi].defined)
+            return fail(ctx, PSWEEP_ESTATE, "frame uses an undefined camera set");
+        const CamSet &C = ctx->sets[csi];
+        if (!fr.ref || fr.ref_pitch < C.ref.width) return fail(ctx, PSWEEP_EINVAL, "bad reference image or pitch");
+        for (int s = 0; s < C.n_src; ++s)
+            if (!fr.src[s] || fr.src_pitch[s] < C.src[s].width)
+                return fail(ctx, PSWEEP_EINVAL, "bad source image or pitch");
+        char *slot = ctx->ws + ctx->off_slots + (size_t)f * ctx->slot_bytes;
+        const psweep_output &O = out[f];
+        int crop_x = 0, crop_y = 0, crop_w = 0, crop_h = 0;
+        if (NL == 2) {
+            crop_x = cfg.level[1].crop_x; crop_y = cfg.level[1].crop_y;
+            crop_w = cfg.level[1].crop_w; crop_h = cfg.level[1].crop_h;
+            if (C.crop_set) { crop_x = C.crop[0]; crop_y = C.crop[1]; crop_w = C.crop[2]; crop_h = C.crop[3]; }
+            if (crop_w <= 0 || crop_x + crop_w > C.ref.width || crop_y + crop_h > C.ref.height)
+                return fail(ctx, PSWEEP_EINVAL, "crop rectangle outside the reference image");
+        }
+        if (sf) {
+            if (cfg.mode == PSWEEP_MODE_SOFT) {
+                if (!O.soft_invdepth || !O.soft_lse) return fail(ctx, PSWEEP_EINVAL, "soft mode needs soft outputs");
+                if (O.soft_pitch != 0 && O.soft_pitch < C.ref.width) return fail(ctx, PSWEEP_EINVAL, "soft pitch");
+            } else if (O.merged.pitch != 0 && O.merged.pitch < C.ref.width) {
+                return fail(ctx, PSWEEP_EINVAL, "output pitch below width");
+            }
+        } else if (O.merged.pitch != 0 && O.merged.pitch < C.ref.width) {
+            return fail(ctx, PSWEEP_EINVAL, "output pitch below width");
+        }
+        int lvl_job[PSWEEP_MAX_LEVELS] = {-1, -1};
+        for (int l = 0; l < NL; ++l) {
+            const psweep_level &L = cfg.level[l];
+            const int ds = L.downsample;
+            const LevelCam rc = level_cam(C.ref, ds, l == 1 ? crop_x : 0, l == 1 ? crop_y : 0, l == 1 ? crop_w : 0,
+                                          l == 1 ? crop_h : 0);
+            const int P = L.n_fronto + L.n_ground;
+            const int hw = L.window / 2;
+            JobDev J;
+            std::memset(&J, 0, sizeof J);
+            if (ds == 2) {
+                J.ref = (const uint8_t *)(slot + ctx->s_ref[l]);
+                J.ref_pitch = C.ref.width / 2;
+            } else {
+                J.ref = fr.ref + (l == 1 ? (int64_t)crop_y * fr.ref_pitch + crop_x : 0);
+                J.ref_pitch = fr.ref_pitch;
+            }
+            J.w = rc.w; J.h = rc.h;
+            J.fx = (float)rc.fx; J.fy = (float)rc.fy; J.cx = (float)rc.cx; J.cy = (float)rc.cy; J.xi = (float)rc.xi;
+            J.inv_fx = (float)(1.0 / rc.fx); J.inv_fy = (float)(1.0 / rc.fy);
+            J.n_src = C.n_src; J.n_fronto = L.n_fronto; J.n_ground = L.n_ground; J.window = L.window;
+            J.best_k = cfg.best_k; J.mode = cfg.mode;
+            J.var_floor_n = (float)(cfg.var_floor * L.window * L.window);
+            for (int a = 0; a < 3; ++a) J.gn[a] = (float)cfg.ground_n[a];
+            J.gd = (float)cfg.ground_d;
+            J.step_f = L.n_fronto > 1 ? (float)((1.0 / L.near_m - 1.0 / L.far_m) / (L.n_fronto - 1)) : 0.0f;
+            J.step_g = L.n_ground > 1 ? (float)((L.h_hi - L.h_lo) / (L.n_ground - 1)) : 0.0f;
+            J.temperature = (float)cfg.temperature;
+            J.htab = (const float *)(slot + ctx->s_htab[l]);
+            J.theta = (const float *)(slot + ctx->s_theta[l]);
+            // outputs
+            if (sf) {
+                if (cfg.mode == PSWEEP_MODE_SOFT) {
+                    J.soft_rho = O.soft_invdepth; J.soft_lse = O.soft_lse;
+                    J.soft_pitch = O.soft_pitch ? O.soft_pitch : C.ref.width;
+                } else {
+                    const psweep_maps &M = O.merged;
+                    J.index = M.index; J.delta = M.delta; J.cost1 = M.cost1; J.cost2 = M.cost2;
+                    J.depth = M.depth; J.z = M.z; J.level_id = M.level;
+                    J.out_pitch = M.pitch ? M.pitch : C.ref.width;
+                }
+            } else {
+                const psweep_maps &M = O.level[l];
+                if (M.index || M.delta || M.cost1 || M.cost2) {
+                    if (!(M.index && M.delta && M.cost1 && M.cost2))
+                        return fail(ctx, PSWEEP_EINVAL, "level maps need index, delta, cost1 and cost2 together");
+                    if (M.pitch != 0 && M.pitch < rc.w) return fail(ctx, PSWEEP_EINVAL, "level map pitch below width");
+                    J.index = M.index; J.delta = M.delta; J.cost1 = M.cost1; J.cost2 = M.cost2;
+                    J.out_pitch = M.pitch ? M.pitch : rc.w;
+                } else {
+                    const size_t plane = align_up((size_t)ctx->ref_w[l] * ctx->ref_h[l] * 4);
+                    char *m = slot + ctx->s_maps[l];
+                    J.index = (int32_t *)m; J.delta = (float *)(m + plane);
+                    J.cost1 = (float *)(m + 2 * plane); J.cost2 = (float *)(m + 3 * plane);
+                    J.out_pitch = rc.w;
+                }
+                J.depth = M.depth; J.z = M.z;
+            }
+            const int TXO = kWave - 2 * hw;
+            const int rows = ctx->tile_rows[l], waves = ctx->tile_waves[l];
+            const int TYO = rows * waves;
+            J.tiles_x = rc.w > 2 * hw ? (rc.w - 2 * hw + TXO - 1) / TXO : 0;
+            J.tiles_y = rc.h > 2 * hw ? (rc.h - 2 * hw + TYO - 1) / TYO : 0;
+            J.first_item = first_item;
+            first_item += J.tiles_x * J.tiles_y;
+            J.rows = rows; J.waves = waves;
+            for (int s = 0; s < C.n_src; ++s) {
+                const LevelCam sc = level_cam(C.src[s], ds, 0, 0, 0, 0);
+                SrcDev &D = J.src[s];
+                D.tex = (const uint32_t *)(slot + ctx->s_tex[l] + align_up((size_t)ctx->src_w[l] * ctx->src_h[l] * 4) * s);
+                D.w = sc.w; D.h = sc.h;
+                D.fx = (float)sc.fx; D.fy = (float)sc.fy; D.cx = (float)sc.cx; D.cy = (float)sc.cy; D.xi = (float)sc.xi;
+                D.wm1 = (float)(sc.w - 1); D.hm1 = (float)(sc.h - 1);
+            }
+            // FP64 setup
+            SetupDev Sd;
+            std::memset(&Sd, 0, sizeof Sd);
+            for (int s = 0; s < C.n_src; ++s) {
+                std::memcpy(Sd.R[s], C.pose[s].R, sizeof(double) * 9);
+                std::memcpy(Sd.t[s], C.pose[s].t, sizeof(double) * 3);
+            }
+            Sd.near_m = L.near_m; Sd.far_m = L.far_m; Sd.h_lo = L.h_lo; Sd.h_hi = L.h_hi;
+            for (int a = 0; a < 3; ++a) Sd.gn[a] = cfg.ground_n[a];
+            Sd.gd = cfg.ground_d;
+            Sd.n_src = C.n_src; Sd.n_fronto = L.n_fronto; Sd.n_ground = L.n_ground;
+            Sd.htab = (float *)(slot + ctx->s_htab[l]);
+            Sd.theta = (float *)(slot + ctx->s_theta[l]);
+            (void)P;
+            // level images
+            PrepDev Pd;
+            std::memset(&Pd, 0, sizeof Pd);
+            Pd.ref_full = fr.ref; Pd.ref_pitch = fr.ref_pitch;
+            Pd.ref_w = C.ref.width; Pd.ref_h = C.ref.height;
+            Pd.ref_level = ds == 2 ? (uint8_t *)(slot + ctx->s_ref[l]) : nullptr;
+            Pd.downsample = ds; Pd.n_src = C.n_src;
+            for (int s = 0; s < C.n_src; ++s) {
+                Pd.src_full[s] = fr.src[s]; Pd.src_pitch[s] = fr.src_pitch[s];
+                Pd.src_w[s] = C.src[s].width; Pd.src_h[s] = C.src[s].height;
+                Pd.tex[s] = (uint32_t *)J.src[s].tex;
+            }
+            // border marks
+            BorderDev Bd;
+            std::memset(&Bd, 0, sizeof Bd);
+            Bd.w = rc.w; Bd.h = rc.h; Bd.hw = hw;
+            Bd.index = J.index; Bd.delta = J.delta; Bd.cost1 = J.cost1; Bd.cost2 = J.cost2;
+            Bd.depth = J.depth; Bd.z = J.z; Bd.level_id = J.level_id; Bd.out_pitch = J.out_pitch;
+            Bd.soft_rho = J.soft_rho; Bd.soft_lse = J.soft_lse; Bd.soft_pitch = J.soft_pitch;
+            lvl_job[l] = (int)jobs.size();
+            jobs.push_back(J);
+            setups.push_back(Sd);
+            preps.push_back(Pd);
+            borders.push_back(Bd);
+            job_frame.push_back(f);
+        }
+        if (!sf) {
+            const psweep_maps &M = O.merged;
+            MergeDev Md;
+            std::memset(&Md, 0, sizeof Md);
+            Md.w = C.ref.width; Md.h = C.ref.height;
+            Md.fx = (float)C.ref.fx; Md.fy = (float)C.ref.fy; Md.cx = (float)C.ref.cx; Md.cy = (float)C.ref.cy;
+            Md.xi = (float)C.ref.xi;
+            for (int a = 0; a < 3; ++a) Md.gn[a] = (float)cfg.ground_n[a];
+            Md.gd = (float)cfg.ground_d;
+            Md.n_levels = NL; Md.ds0 = cfg.level[0].downsample;
+            const JobDev &J0 = jobs[lvl_job[0]];
+            Md.low_w = J0.w; Md.low_h = J0.h;
+            Md.low_index = J0.index; Md.low_delta = J0.delta; Md.low_c1 = J0.cost1; Md.low_c2 = J0.cost2;
+            Md.low_pitch = J0.out_pitch; Md.low_theta = J0.theta; Md.low_nf = J0.n_fronto;
+            Md.low_step_f = J0.step_f; Md.low_step_g = J0.step_g;
+            if (NL == 2) {
+                const JobDev &J1 = jobs[lvl_job[1]];
+                Md.crop_x = crop_x; Md.crop_y = crop_y; Md.crop_w = crop_w; Md.crop_h = crop_h;
+                Md.crop_index = J1.index; Md.crop_delta = J1.delta; Md.crop_c1 = J1.cost1; Md.crop_c2 = J1.cost2;
+                Md.crop_pitch = J1.out_pitch; Md.crop_theta = J1.theta; Md.crop_nf = J1.n_fronto;
+                Md.crop_step_f = J1.step_f; Md.crop_step_g = J1.step_g;
+                Md.crop_near = (float)cfg.level[1].near_m;
+            }
+            Md.depth = M.depth; Md.z = M.z; Md.delta = M.delta; Md.cost1 = M.cost1; Md.cost2 = M.cost2;
+            Md.index = M.index; Md.level = M.level;
+            Md.out_pitch = M.pitch ? M.pitch : C.ref.width;
+            merges.push_back(Md);
+        }
+    }
+    // compact blob: records at fixed offsets of the table region
+    const int nj = (int)jobs.size(), nm = (int)merges.size();
+    blob.nj = nj; blob.nm = nm;
+    blob.jobs = 0;
+    blob.setups = align_up(sizeof(JobDev) * nj);
+    blob.preps = blob.setups + align_up(sizeof(SetupDev) * nj);
+    blob.borders = blob.preps + align_up(sizeof(PrepDev) * nj);
+    blob.merges = blob.borders + align_up(sizeof(BorderDev) * nj);
+    const size_t total = blob.merges + align_up(sizeof(MergeDev) * (nm > 0 ? nm : 1));
+    if (total > ctx->table_bytes) return fail(ctx, PSWEEP_EINVAL, "too many frames for the table region");
+    blob.bytes.assign(total, 0);
+    std::memcpy(blob.bytes.data() + blob.jobs, jobs.data(), sizeof(JobDev) * nj);
+    std::memcpy(blob.bytes.data() + blob.setups, setups.data(), sizeof(SetupDev) * nj);
+    std::memcpy(blob.bytes.data() + blob.preps, preps.data(), sizeof(PrepDev) * nj);
+    std::memcpy(blob.bytes.data() + blob.borders, borders.data(), sizeof(BorderDev) * nj);
+    if (nm) std::memcpy(blob.bytes.data() + blob.merges, merges.data(), sizeof(MergeDev) * nm);
+    (void)tbase;
+    return PSWEEP_OK;
+}
+
+// Enqueue the kernels of one run whose tables sit at device address `tb`.
+psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hipStream_t stream, bool do_setup,
+                      bool timed, const std::vector<JobDev> *host_jobs) {
+    const psweep_config &cfg = ctx->cfg;
+    const int nj = blob.nj;
+    JobDev *dj = (JobDev *)(tb + blob.jobs);
+    SetupDev *dsu = (SetupDev *)(tb + blob.setups);
+    PrepDev *dp = (PrepDev *)(tb + blob.preps);
+    BorderDev *db = (BorderDev *)(tb + blob.borders);
+    MergeDev *dm = (MergeDev *)(tb + blob.merges);
+    int maxPS = 1, maxS = 1;
+    for (int j = 0; j < nj; ++j) {
+        const JobDev &J = (*host_jobs)[j];
+        maxPS = std::max(maxPS, (J.n_fronto + J.n_ground) * J.n_src);
+        maxS = std::max(maxS, J.n_src);
+    }
+    if (do_setup) {
+        void *a[] = {&dsu};
+        PSW_HIP(hipLaunchKernel(psw_setup_kernel(), dim3((maxPS + 255) / 256, nj), dim3(256), a, 0, stream), "setup");
+    }
+    {
+        void *a[] = {&dp};
+        PSW_HIP(hipLaunchKernel(psw_prep_kernel(), dim3(256, 1 + maxS, nj), dim3(256), a, 0, stream), "prep");
+    }
+    {
+        void *a[] = {&db};
+        PSW_HIP(hipLaunchKernel(psw_border_kernel(), dim3(32, nj), dim3(256), a, 0, stream), "border");
+    }
+    const int store = cfg.storage, soft = cfg.mode == PSWEEP_MODE_SOFT ? 1 : 0;
+    if (timed) {
+        const size_t need = cfg.launch == PSWEEP_LAUNCH_PERSISTENT ? 1 : (size_t)nj;
+        while (ctx->ev0.size() < need) {
+            hipEvent_t e0, e1;
+            PSW_HIP(hipEventCreate(&e0), "event");
+            PSW_HIP(hipEventCreate(&e1), "event");
+            ctx->ev0.push_back(e0);
+            ctx->ev1.push_back(e1);
+        }
+        ctx->n_timed = 0;
+    }
+    if (cfg.launch == PSWEEP_LAUNCH_GRID) {
+        for (int j = 0; j < nj; ++j) {
+            const JobDev &J = (*host_jobs)[j];
+            const int nt = J.tiles_x * J.tiles_y;
+            if (nt == 0) continue;
+            const KernelEntry *e = find_kernel(J.window, J.rows, J.waves, J.n_src, store, soft, 0);
+            if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no kernel for this window/tile/sources/storage");
+            JobDev *jp = dj + j;
+            void *a[] = {&jp};
+            const int grid = 8 * ((nt + 7) / 8);
+            if (timed) PSW_HIP(hipEventRecord(ctx->ev0[ctx->n_timed], stream), "event record");
+            PSW_HIP(hipLaunchKernel(e->fn, dim3(grid), dim3(kWave * J.waves), a, e->lds, stream), "sweep");
+            if (timed) PSW_HIP(hipEventRecord(ctx->ev1[ctx->n_timed++], stream), "event record");
+        }
+    } else {
+        int n_items = 0, n_src = (*host_jobs)[0].n_src;
+        for (int j = 0; j < nj; ++j) {
+            const JobDev &J = (*host_jobs)[j];
+            n_items += J.tiles_x * J.tiles_y;
+            if (J.n_src != n_src) return fail(ctx, PSWEEP_EUNSUPPORTED, "persistent launch needs one source count");
+            if (J.rows != ctx->tile_rows[0] || J.waves != ctx->tile_waves[0])
+                return fail(ctx, PSWEEP_EUNSUPPORTED, "persistent launch needs one tile shape");
+        }
+        const KernelEntry *e = find_kernel(0, ctx->tile_rows[0], ctx->tile_waves[0], n_src, store, 0, 1);
+        if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no persistent kernel for this tile/sources/storage");
+        int *counter = (int *)(ctx->ws + ctx->off_counter[which]);
+        {
+            void *a[] = {&counter};
+            PSW_HIP(hipLaunchKernel(psw_reset_kernel(), dim3(1), dim3(64), a, 0, stream), "reset");
+        }
+        int dev = 0, n_cu = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) n_cu = prop.multiProcessorCount;
+        }
+        int per_cu = 1;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->fn, kWave * ctx->tile_waves[0], e->lds);
+        if (per_cu < 1) per_cu = 1;
+        const int grid = std::min(n_items, n_cu * per_cu);
+        if (grid > 0) {
+            void *a[] = {&dj, (void *)&nj, &n_items, &counter};
+            int nj_v = nj;
+            a[1] = &nj_v;
+            if (timed) PSW_HIP(hipEventRecord(ctx->ev0[0], stream), "event record");
+            PSW_HIP(hipLaunchKernel(e->fn, dim3(grid), dim3(kWave * ctx->tile_waves[0]), a, e->lds, stream), "sweep");
+            if (timed) { PSW_HIP(hipEventRecord(ctx->ev1[0], stream), "event record"); ctx->n_timed = 1; }
+        }
+    }
+    if (blob.nm > 0) {
+        void *a[] = {&dm};
+        PSW_HIP(hipLaunchKernel(psw_merge_kernel(), dim3(512, blob.nm), dim3(256), a, 0, stream), "merge");
+    }
+    return PSWEEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames, const psweep_output *out,
+                         void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (!ctx->ws) return fail(ctx, PSWEEP_ESTATE, "psweep_set_workspace has not been called");
+    if (!frames || !out) return fail(ctx, PSWEEP_EINVAL, "NULL frames or outputs");
+    if (n_frames < 1 || n_frames > ctx->cfg.max_frames) return fail(ctx, PSWEEP_EINVAL, "n_frames out of range");
+    if (ctx->cfg.mode == PSWEEP_MODE_SOFT && n_frames != 1) return fail(ctx, PSWEEP_EINVAL, "soft mode runs one frame");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    Blob blob;
+    std::vector<int> job_frame;
+    char *tb = ctx->ws + ctx->off_table[0];
+    psweep_status st = build_tables(ctx, frames, n_frames, out, tb, blob, job_frame);
+    if (st != PSWEEP_OK) return st;
+    std::vector<JobDev> hj(blob.nj);
+    std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);
+    // upload the tables when they changed (the device copy stays valid: only
+    // psweep_run writes this region)
+    const bool changed = blob.bytes != ctx->last_table;
+    if (changed) {
+        const int b = ctx->staging_idx;
+        if (ctx->staging_pending[b]) {
+            PSW_HIP(hipEventSynchronize(ctx->staging_ev[b]), "staging wait");
+            ctx->staging_pending[b] = false;
+        }
+        std::memcpy(ctx->staging[b], blob.bytes.data(), blob.bytes.size());
+        PSW_HIP(hipMemcpyAsync(tb, ctx->staging[b], blob.bytes.size(), hipMemcpyHostToDevice, stream), "table upload");
+        PSW_HIP(hipEventRecord(ctx->staging_ev[b], stream), "staging event");
+        ctx->staging_pending[b] = true;
+        ctx->staging_idx ^= 1;
+        ctx->last_table = blob.bytes;
+    }
+    const bool do_setup = changed || ctx->setup_version != ctx->cam_version;
+    st = enqueue(ctx, blob, tb, 0, stream, do_setup, ctx->timing, &hj);
+    if (st != PSWEEP_OK) { ctx->last_table.clear(); return st; }
+    ctx->setup_version = ctx->cam_version;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch");
+    if (ctx->cfg.mode == PSWEEP_MODE_SOFT) {
+        ctx->soft_ready = true;
+        ctx->soft_frame = frames[0];
+        ctx->soft_rho = out[0].soft_invdepth;
+        ctx->soft_lse = out[0].soft_lse;
+        ctx->soft_pitch = out[0].soft_pitch ? out[0].soft_pitch : hj[0].w;
+        ctx->soft_job_off = ctx->off_table[0] + blob.jobs;
+    } else {
+        ctx->soft_ready = false;
+    }
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_sweep_kernel_ms(psweep_ctx *ctx, double *ms, int32_t *n_launches) {
+    if (!ctx || !ms) return PSWEEP_EINVAL;
+    if (ctx->n_timed == 0) return fail(ctx, PSWEEP_ESTATE, "no timed sweep launches (enable timing first)");
+    double sum = 0;
+    for (int i = 0; i < ctx->n_timed; ++i) {
+        float t = 0;
+        hipError_t e = hipEventElapsedTime(&t, ctx->ev0[i], ctx->ev1[i]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "event elapsed");
+        sum += t;
+    }
+    *ms = sum / ctx->n_timed;
+    if (n_launches) *n_launches = ctx->n_timed;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                                   const psweep_output *out, void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (!ctx->ws) return fail(ctx, PSWEEP_ESTATE, "psweep_set_workspace has not been called");
+    if (!frames || !out || n_frames < 1 || n_frames > ctx->cfg.max_frames)
+        return fail(ctx, PSWEEP_EINVAL, "bad frames");
+    if (ctx->cfg.mode == PSWEEP_MODE_SOFT) return fail(ctx, PSWEEP_EUNSUPPORTED, "graphs are for the WTA sweep");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    Blob blob;
+    std::vector<int> job_frame;
+    char *tb = ctx->ws + ctx->off_table[1];
+    psweep_status st = build_tables(ctx, frames, n_frames, out, tb, blob, job_frame);
+    if (st != PSWEEP_OK) return st;
+    std::vector<JobDev> hj(blob.nj);
+    std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);
+    // the graph's own table region is filled once, outside the graph
+    PSW_HIP(hipMemcpy(tb, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice), "graph table upload");
+    if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+    if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+    PSW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    st = enqueue(ctx, blob, tb, 1, stream, true, false, &hj);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &g);
+    if (st != PSWEEP_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(ctx, e, "end capture");
+    ctx->graph = g;
+    PSW_HIP(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+    ctx->soft_ready = false;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_graph_launch(psweep_ctx *ctx, void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (!ctx->gexec) return fail(ctx, PSWEEP_ESTATE, "no captured graph");
+    PSW_HIP(hipGraphLaunch(ctx->gexec, (hipStream_t)hip_stream), "graph launch");
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_invdepth, float *const *d_grad_src,
+                                         double *d_grad_pose, void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (!ctx->soft_ready) return fail(ctx, PSWEEP_ESTATE, "backward needs a preceding soft-mode psweep_run");
+    if (!d_grad_invdepth || !d_grad_src || !d_grad_pose) return fail(ctx, PSWEEP_EINVAL, "NULL gradient buffer");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const JobDev *job = (const JobDev *)(ctx->ws + ctx->soft_job_off);
+    const CamSet &C = ctx->sets[ctx->soft_frame.camera_set];
+    for (int s = 0; s < C.n_src; ++s)
+        if (!d_grad_src[s]) return fail(ctx, PSWEEP_EINVAL, "NULL source gradient");
+    const void *zk = psw_zero_kernel();
+    for (int s = 0; s < C.n_src; ++s) {
+        float *p = d_grad_src[s];
+        int64_t n = (int64_t)C.src[s].width * C.src[s].height;
+        void *a[] = {&p, &n};
+        PSW_HIP(hipLaunchKernel(zk, dim3(256), dim3(256), a, 0, stream), "zero");
+    }
+    {
+        float *p = (float *)d_grad_pose;
+        int64_t n = (int64_t)C.n_src * 12;   // doubles as pairs of floats
+        void *a[] = {&p, &n};
+        PSW_HIP(hipLaunchKernel(zk, dim3(1), dim3(256), a, 0, stream), "zero");
+    }
+    const int win = ctx->cfg.level[0].window;
+    const void *bk = psw_backward_kernel(win, C.n_src);
+    if (!bk) return fail(ctx, PSWEEP_EUNSUPPORTED, "no backward kernel for this window / source count");
+    const size_t lds = psw_backward_lds(win, C.n_src);
+    const int hw = win / 2;
+    const int w = C.ref.width, h = C.ref.height;
+    const int tx = (w - 2 * hw + (kWave - 2 * hw) - 1) / (kWave - 2 * hw);
+    const int ty = (h - 2 * hw + 31) / 32;
+    if (tx <= 0 || ty <= 0) return PSWEEP_OK;
+    float *g0 = d_grad_src[0], *g1 = C.n_src > 1 ? d_grad_src[1] : nullptr;
+    float *g2 = C.n_src > 2 ? d_grad_src[2] : nullptr, *g3 = C.n_src > 3 ? d_grad_src[3] : nullptr;
+    const float *rho = ctx->soft_rho, *lse = ctx->soft_lse;
+    int64_t sp = ctx->soft_pitch;
+    void *a[] = {(void *)&job, (void *)&d_grad_invdepth, (void *)&rho, (void *)&lse, &sp,
+                 &g0, &g1, &g2, &g3, &d_grad_pose};
+    PSW_HIP(hipLaunchKernel(bk, dim3(tx, ty), dim3(256), a, lds, stream), "backward");
+    return PSWEEP_OK;
+}
+
+void psweep_destroy(psweep_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    for (int b = 0; b < 2; ++b) {
+        if (ctx->staging[b]) (void)hipHostFree(ctx->staging[b]);
+        if (ctx->staging_ev[b]) (void)hipEventDestroy(ctx->staging_ev[b]);
+    }
+    for (auto e : ctx->ev0) (void)hipEventDestroy(e);
+    for (auto e : ctx->ev1) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// Small kernels around the sweep: FP64 per-plane setup, level images,
+// border marks, the work counter reset and the level merge.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sweep_common.h"
+
+namespace psw {
+
+// ---------------------------------------------------------------------------
+// per-plane parameters in FP64 (H = R + t n^T / d rounded to float)
+// ---------------------------------------------------------------------------
+__global__ void setup_kernel(const SetupDev *__restrict__ jobs) {
+    const SetupDev &J = jobs[blockIdx.y];
+    const int P = J.n_fronto + J.n_ground, S = J.n_src;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P * S; e += gridDim.x * blockDim.x) {
+        const int k = e / S, s = e % S;
+        double n[3], d, theta;
+        if (k < J.n_fronto) {
+            double rho = 1.0 / J.far_m;
+            if (J.n_fronto > 1) rho += k * (1.0 / J.near_m - 1.0 / J.far_m) / (J.n_fronto - 1);
+            n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+            d = 1.0 / rho;
+            theta = rho;
+        } else {
+            const int g = k - J.n_fronto;
+            double h = J.h_lo;
+            if (J.n_ground > 1) h += g * (J.h_hi - J.h_lo) / (J.n_ground - 1);
+            n[0] = J.gn[0]; n[1] = J.gn[1]; n[2] = J.gn[2];
+            d = J.gd - h;
+            theta = h;
+        }
+        float *out = J.htab + (size_t)(k * S + s) * 9;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) out[c * 3 + r] = (float)(J.R[s][r * 3 + c] + J.t[s][r] * n[c] / d);
+        if (s == 0) J.theta[k] = (float)theta;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// level images: 2x2 box-downsampled reference, 2x2-quad packed source texels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t level_pix(const uint8_t *img, int64_t pitch, int x, int y, int ds) {
+    if (ds == 1) return img[(int64_t)y * pitch + x];
+    const uint8_t *p = img + (int64_t)(2 * y) * pitch + 2 * x;
+    return ((uint32_t)p[0] + p[1] + p[pitch] + p[pitch + 1] + 2u) >> 2;
+}
+
+// blockIdx.z: prep job; blockIdx.y: 0 = reference, 1 + s = source s
+__global__ void prep_kernel(const PrepDev *__restrict__ preps) {
+    const PrepDev &P = preps[blockIdx.z];
+    const int which = blockIdx.y;
+    const int ds = P.downsample;
+    if (which == 0) {
+        if (!P.ref_level) return;
+        const int lw = P.ref_w / ds, lh = P.ref_h / ds;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lw * lh; e += gridDim.x * blockDim.x) {
+            const int x = e % lw, y = e / lw;
+            P.ref_level[e] = (uint8_t)level_pix(P.ref_full, P.ref_pitch, x, y, ds);
+        }
+        return;
+    }
+    const int s = which - 1;
+    if (s >= P.n_src) return;
+    const int lw = P.src_w[s] / ds, lh = P.src_h[s] / ds;
+    const uint8_t *img = P.src_full[s];
+    const int64_t pitch = P.src_pitch[s];
+    uint32_t *tex = P.tex[s];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lw * lh; e += gridDim.x * blockDim.x) {
+        const int x = e % lw, y = e / lw;
+        const int x1 = min(x + 1, lw - 1), y1 = min(y + 1, lh - 1);
+        const uint32_t p00 = level_pix(img, pitch, x, y, ds), p10 = level_pix(img, pitch, x1, y, ds);
+        const uint32_t p01 = level_pix(img, pitch, x, y1, ds), p11 = level_pix(img, pitch, x1, y1, ds);
+        tex[e] = p00 | (p10 << 8) | (p01 << 16) | (p11 << 24);
+    }
+}
+
+// invalid marks on the frame of pixels whose window leaves the image
+__global__ void border_kernel(const BorderDev *__restrict__ bs) {
+    const BorderDev &B = bs[blockIdx.y];
+    const int w = B.w, h = B.h, hw = B.hw;
+    const int band = min(hw, h);             // rows at top and at bottom
+    const int top = band * w;
+    const int side_rows = max(h - 2 * band, 0);
+    const int total = 2 * top + side_rows * 2 * min(hw, w);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        int x, y;
+        if (e < 2 * top) {
+            const int r = e / w;
+            x = e % w;
+            y = r < band ? r : h - 2 * band + r;
+        } else {
+            const int q = e - 2 * top, cw = min(hw, w);
+            const int r = q / (2 * cw), c = q % (2 * cw);
+            y = band + r;
+            x = c < cw ? c : w - 2 * cw + c;
+        }
+        if (x < 0 || x >= w || y < 0 || y >= h) continue;
+        const int64_t o = (int64_t)y * B.out_pitch + x;
+        if (B.index) B.index[o] = -1;
+        if (B.delta) B.delta[o] = 0.0f;
+        if (B.cost1) B.cost1[o] = PSW_INF;
+        if (B.cost2) B.cost2[o] = PSW_INF;
+        if (B.depth) B.depth[o] = __builtin_nanf("");
+        if (B.z) B.z[o] = __builtin_nanf("");
+        if (B.level_id) B.level_id[o] = 255;
+        if (B.soft_rho) {
+            const int64_t so = (int64_t)y * B.soft_pitch + x;
+            B.soft_rho[so] = __builtin_nanf("");
+            B.soft_lse[so] = -PSW_INF;
+        }
+    }
+}
+
+__global__ void reset_counter_kernel(int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// level merge (Sec. III-A multi-scale strategy; reading: nearest-neighbour
+// plane from the low level with the range recomputed on the full-resolution
+// ray, replaced inside the crop by the crop result when that is valid and the
+// low result is invalid or at least as far as the crop's nearest plane)
+// ---------------------------------------------------------------------------
+__global__ void merge_kernel(const MergeDev *__restrict__ ms) {
+    const MergeDev &M = ms[blockIdx.y];
+    const int n = M.w * M.h;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int i = e % M.w, j = e / M.w;
+        const float x = ((float)i - M.cx) / M.fx, y = ((float)j - M.cy) / M.fy;
+        float eta;
+        const float t = ray_tau(x, y, M.xi, &eta);
+        const float rz = eta * t;
+        const float ng = eta * fmaf(M.gn[0], x, fmaf(M.gn[1], y, M.gn[2] * t));
+        float lam_lo = __builtin_nanf("");
+        int64_t src_lo = -1;
+        const int il = i / M.ds0, jl = j / M.ds0;
+        if (il < M.low_w && jl < M.low_h) {
+            const int64_t le = (int64_t)jl * M.low_pitch + il;
+            const int k = M.low_index[le];
+            if (k >= 0) {
+                const bool fr = k < M.low_nf;
+                const float th = M.low_theta[k] + M.low_delta[le] * (fr ? M.low_step_f : M.low_step_g);
+                if (fr) { if (rz > 0.0f) lam_lo = 1.0f / (th * rz); }
+                else if (ng > 0.0f) lam_lo = (M.gd - th) / ng;
+                if (!__builtin_isnan(lam_lo)) src_lo = le;
+            }
+        }
+        float lam_c = __builtin_nanf("");
+        int64_t src_c = -1;
+        if (M.n_levels > 1 && i >= M.crop_x && i < M.crop_x + M.crop_w && j >= M.crop_y && j < M.crop_y + M.crop_h) {
+            const int64_t ce = (int64_t)(j - M.crop_y) * M.crop_pitch + (i - M.crop_x);
+            const int k = M.crop_index[ce];
+            if (k >= 0) {
+                const bool fr = k < M.crop_nf;
+                const float th = M.crop_theta[k] + M.crop_delta[ce] * (fr ? M.crop_step_f : M.crop_step_g);
+                lam_c = fr ? 1.0f / (th * rz) : (M.gd - th) / ng;
+                src_c = ce;
+            }
+        }
+        const float z_lo = lam_lo * rz;
+        const int64_t o = (int64_t)j * M.out_pitch + i;
+        int lev = 255;
+        float lam = __builtin_nanf("");
+        if (src_c >= 0 && (src_lo < 0 || z_lo >= M.crop_near)) { lev = 1; lam = lam_c; }
+        else if (src_lo >= 0) { lev = 0; lam = lam_lo; }
+        if (M.depth) M.depth[o] = lam;
+        if (M.z) M.z[o] = lam * rz;
+        if (M.level) M.level[o] = (uint8_t)lev;
+        if (M.index) M.index[o] = lev == 1 ? M.crop_index[src_c] : (lev == 0 ? M.low_index[src_lo] : -1);
+        if (M.delta) M.delta[o] = lev == 1 ? M.crop_delta[src_c] : (lev == 0 ? M.low_delta[src_lo] : 0.0f);
+        if (M.cost1) M.cost1[o] = lev == 1 ? M.crop_c1[src_c] : (lev == 0 ? M.low_c1[src_lo] : PSW_INF);
+        if (M.cost2) M.cost2[o] = lev == 1 ? M.crop_c2[src_c] : (lev == 0 ? M.low_c2[src_lo] : PSW_INF);
+    }
+}
+
+}  // namespace psw
+
+extern "C" {
+const void *psw_setup_kernel() { return (const void *)&psw::setup_kernel; }
+const void *psw_prep_kernel() { return (const void *)&psw::prep_kernel; }
+const void *psw_border_kernel() { return (const void *)&psw::border_kernel; }
+const void *psw_reset_kernel() { return (const void *)&psw::reset_counter_kernel; }
+const void *psw_merge_kernel() { return (const void *)&psw::merge_kernel; }
+}

@@ -1,0 +1,483 @@
+#pragma once
+// Sweep kernel templates of the fisheye plane-sweep library (gfx950).
+//
+// Method (Cui et al., Sec. III-A; camera model Sec. III-C Eq. (1)): every
+// reference pixel's ray is cut with each plane hypothesis, the point is
+// projected into each source with the unified model and sampled bilinearly;
+// the cost of a (pixel, plane, source) is (1 - ZNCC) / 2 over a square
+// window; the best few source costs are averaged; the best plane per pixel
+// wins, refined by a parabola through its neighbours.
+//
+// Layout on the chip (one workgroup = NW waves = one tile):
+//   * a wave owns 64 consecutive sample columns (lane = column) and R output
+//     rows; the tile's 64 - (W-1) output columns are the lanes whose whole
+//     window lies inside the 64;
+//   * per plane, the NW waves warp the tile's NW*R + W - 1 sample rows of
+//     every source (rows interleaved across waves) into LDS;
+//   * each wave then runs down its R + W - 1 rows with per-lane running
+//     vertical sums of b, b^2 and a*b (one set per source, in registers) and
+//     forms horizontal window sums across lanes with ds_bpermute/DPP shifts;
+//   * ZNCC, best-K aggregation and the winner-take-all (or soft-argmin)
+//     state of the wave's R pixels per lane stay in registers for the whole
+//     sweep.  Nothing per-plane ever leaves the chip.
+// Invalid samples (plane missed, point behind the model's viewpoint, outside
+// the source) are staged as -0.0: they add nothing to the sums and a lane
+// keeps the row of its last invalid sample, so a window is unusable when
+// that row is inside it (vertical), dilated across lanes on the wave's
+// 64-bit ballot (horizontal).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "psweep_internal.h"
+
+namespace psw {
+
+#define PSW_INF __builtin_huge_valf()
+
+// ---------------------------------------------------------------------------
+// staging precision of warped samples (centred: b - 128)
+// ---------------------------------------------------------------------------
+template <int STORE> struct Stage;
+template <> struct Stage<0> {
+    using T = float;
+    static __device__ __forceinline__ T put(float v) { return v; }
+    static __device__ __forceinline__ float get(T v) { return v; }
+};
+template <> struct Stage<1> {
+    using T = _Float16;
+    static __device__ __forceinline__ T put(float v) { return (_Float16)v; }
+    static __device__ __forceinline__ float get(T v) { return (float)v; }
+};
+template <> struct Stage<2> {
+    using T = uint16_t;   // bfloat16 bits, round to nearest even
+    static __device__ __forceinline__ T put(float v) {
+        uint32_t u = __float_as_uint(v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+    static __device__ __forceinline__ float get(T v) { return __uint_as_float(((uint32_t)v) << 16); }
+};
+
+#define PSW_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ PSW_GLOBAL T *gptr(T *p) { return (PSW_GLOBAL T *)p; }
+template <typename T> __device__ __forceinline__ const PSW_GLOBAL T *gptr(const T *p) { return (const PSW_GLOBAL T *)p; }
+// read-only tables written before the launch: scalar loads
+#define PSW_CONST __attribute__((address_space(4)))
+template <typename T> __device__ __forceinline__ const PSW_CONST T *cptr(const T *p) { return (const PSW_CONST T *)p; }
+
+__device__ __forceinline__ bool is_neg_zero(float v) { return __float_as_uint(v) == 0x80000000u; }
+
+// value of v held by lane (lane - d); lanes wrap (only interior lanes are used)
+__device__ __forceinline__ float lane_from(float v, int addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ int lane_from_i(int v, int addr) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+__device__ __forceinline__ float shr1(float v) {   // lane l gets v[l-1] (lane 0 keeps 0)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ int shr1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+
+// Byte addresses for ds_bpermute: lane (lane - d) for the shifts a window
+// sum of side WIN needs (d = 2, 4 for the block sums, then the final
+// placements, which are all in [-7, 7]).
+struct Shifts {
+    int a[16];   // a[d + 7] = ((lane - d) & 63) * 4
+    __device__ __forceinline__ void init(int lane) {
+#pragma unroll
+        for (int d = -7; d <= 8; ++d) a[d + 7] = ((lane - d) & 63) << 2;
+    }
+    __device__ __forceinline__ int at(int d) const { return a[d + 7]; }
+};
+
+// Sum of v over lanes [l - h, l + h] (W = 2h + 1), built from power-of-two
+// block sums B_n[l] = sum v[l-n+1 .. l] placed at the window's right end.
+template <int WIN, typename T, typename SHR1, typename FROM>
+__device__ __forceinline__ T window_sum(T v, const Shifts &sh, SHR1 s1, FROM from) {
+    constexpr int h = WIN / 2;
+    T b1 = v;
+    T b2 = v + s1(v);
+    T b4 = (WIN >= 5) ? b2 + from(b2, sh.at(2)) : b2;
+    T b8 = (WIN >= 9) ? b4 + from(b4, sh.at(4)) : b4;
+    T acc = 0;
+    int pos = h;   // right end of the uncovered part, relative to l
+    if (WIN & 8) { acc += from(b8, sh.at(-pos)); pos -= 8; }
+    if (WIN & 4) { acc += from(b4, sh.at(-pos)); pos -= 4; }
+    if (WIN & 2) { acc += from(b2, sh.at(-pos)); pos -= 2; }
+    if (WIN & 1) { acc += (pos == 0) ? b1 : from(b1, sh.at(-pos)); }
+    return acc;
+}
+template <int WIN>
+__device__ __forceinline__ float wsum(float v, const Shifts &sh) {
+    return window_sum<WIN>(v, sh, shr1, lane_from);
+}
+template <int WIN>
+__device__ __forceinline__ int wsum_i(int v, const Shifts &sh) {
+    return window_sum<WIN>(v, sh, shr1_i, lane_from_i);
+}
+
+// lanes whose window [l-h, l+h] contains a lane with bit set in m
+template <int WIN>
+__device__ __forceinline__ uint64_t dilate(uint64_t m) {
+    uint64_t d = m;
+#pragma unroll
+    for (int s = 1; s <= WIN / 2; ++s) d |= (m << s) | (m >> s);
+    return d;
+}
+
+// Scale-free ray (x, y, tau) of a normalized point: Eq. (1) gives the unit
+// ray eta * (x, y, 1 - xi / eta); tau = 1 - xi / eta = (sq - xi q) / (xi + sq)
+// with q = x^2 + y^2, sq = sqrt(1 + (1 - xi^2) q).  Also eta.
+__device__ __forceinline__ float ray_tau(float x, float y, float xi, float *eta) {
+    float q = fmaf(x, x, y * y);
+    float sq = __builtin_amdgcn_sqrtf(fmaf(1.0f - xi * xi, q, 1.0f));
+    if (eta) *eta = (xi + sq) / (q + 1.0f);
+    return (sq - xi * q) / (xi + sq);
+}
+
+// Mean of the K smallest valid costs (invalid = +inf) of S <= 4 sources,
+// summed in ascending order; +inf if none is valid.
+template <int S>
+__device__ __forceinline__ float aggregate(const float c[4], int K) {
+    float m0, m1, m2, m3;
+    if (S == 1) {
+        return c[0];
+    } else if (S == 2) {
+        m0 = fminf(c[0], c[1]); m1 = fmaxf(c[0], c[1]); m2 = PSW_INF; m3 = PSW_INF;
+    } else if (S == 3) {
+        m0 = __builtin_fminf(c[0], __builtin_fminf(c[1], c[2]));
+        m1 = __builtin_amdgcn_fmed3f(c[0], c[1], c[2]);
+        m2 = __builtin_fmaxf(c[0], __builtin_fmaxf(c[1], c[2]));
+        m3 = PSW_INF;
+    } else {
+        const float a0 = fminf(c[0], c[1]), a1 = fmaxf(c[0], c[1]);
+        const float a2 = fminf(c[2], c[3]), a3 = fmaxf(c[2], c[3]);
+        const float t0 = fmaxf(a0, a2), t1 = fminf(a1, a3);
+        m0 = fminf(a0, a2); m3 = fmaxf(a1, a3);
+        m1 = fminf(t0, t1); m2 = fmaxf(t0, t1);
+    }
+    float acc = m0, cnt = 1.0f;
+    if (K >= 2) { const bool f = m1 < PSW_INF; acc += f ? m1 : 0.f; cnt += f ? 1.f : 0.f; }
+    if (S >= 3 && K >= 3) { const bool f = m2 < PSW_INF; acc += f ? m2 : 0.f; cnt += f ? 1.f : 0.f; }
+    if (S >= 4 && K >= 4) { const bool f = m3 < PSW_INF; acc += f ? m3 : 0.f; cnt += f ? 1.f : 0.f; }
+    return (m0 < PSW_INF) ? acc * __builtin_amdgcn_rcpf(cnt) : PSW_INF;
+}
+
+// ---------------------------------------------------------------------------
+// the sweep of one tile
+// ---------------------------------------------------------------------------
+template <int WIN, int R, int NW, int S, int STORE, bool SOFT>
+struct Tile {
+    static constexpr int HW = WIN / 2;
+    static constexpr int TXO = kWave - 2 * HW;       // output columns per tile
+    static constexpr int TYO = NW * R;               // output rows per tile
+    static constexpr int T = TYO + 2 * HW;           // sample rows per tile
+    static constexpr int NWR = (T + NW - 1) / NW;    // warp rows per wave
+    static constexpr int VR = R + 2 * HW;            // rows each wave runs down
+    using St = Stage<STORE>;
+    using ST = typename St::T;
+
+    static constexpr size_t lds_bytes() { return (size_t)S * T * kWave * sizeof(ST); }
+
+    __device__ static void run(const JobDev *__restrict__ Jp, int tile_x, int tile_y, char *smem) {
+        const JobDev &J = *Jp;
+        ST *tile = reinterpret_cast<ST *>(smem);
+        const int lane = threadIdx.x & (kWave - 1);
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        const int W = J.w, H = J.h;
+        const int sc = tile_x * TXO + lane;            // sample column of this lane
+        const int sr0 = tile_y * TYO;                  // first sample row of the tile
+        const int or0 = sr0 + wave * R + HW;           // first output row of this wave
+        const float xi = J.xi;
+        const float x = ((float)sc - J.cx) * J.inv_fx;
+
+        Shifts sh;
+        sh.init(lane);
+
+        // --- plane-independent per-lane state -------------------------------
+        float yw[NWR];   // wave-uniform
+#pragma unroll
+        for (int i = 0; i < NWR; ++i) {
+            const int v = sr0 + wave + NW * i;
+            yw[i] = ((float)v - J.cy) * J.inv_fy;
+        }
+        float av[VR];          // centred reference intensities of the rows this wave runs down
+        {
+            const bool col_in = sc < W;
+#pragma unroll
+            for (int m = 0; m < VR; ++m) {
+                const int v = sr0 + wave * R + m;
+                av[m] = (col_in && v < H) ? (float)gptr(J.ref)[(int64_t)v * J.ref_pitch + sc] - 128.0f : 0.0f;
+            }
+        }
+        // reference window statistics of the wave's output pixels (exact in
+        // integers: |a'| <= 128, window sums of a'^2 < 2^24)
+        float mean_a[R], isd_a[R];
+        uint32_t pos_ok = 0, ref_ok = 0;
+        {
+            const float N = (float)(WIN * WIN);
+            int va = 0, vaa = 0;
+#pragma unroll
+            for (int m = 0; m < VR; ++m) {
+                const int a = (int)av[m];
+                va += a; vaa += a * a;
+                if (m >= WIN) {
+                    const int ao = (int)av[m - WIN];
+                    va -= ao; vaa -= ao * ao;
+                }
+                if (m >= WIN - 1) {
+                    const int i = m - (WIN - 1);
+                    const int sa = wsum_i<WIN>(va, sh), saa = wsum_i<WIN>(vaa, sh);
+                    const int nvar = WIN * WIN * saa - sa * sa;          // N^2 * variance, exact
+                    const float var_a = (float)nvar / N;                 // sum of squared deviations
+                    const int orow = or0 + i;
+                    const bool p = lane >= HW && lane < kWave - HW && sc <= W - 1 - HW && orow <= H - 1 - HW;
+                    const bool r = p && var_a > J.var_floor_n;
+                    pos_ok |= (p ? 1u : 0u) << i;
+                    ref_ok |= (r ? 1u : 0u) << i;
+                    mean_a[i] = (float)sa / N;
+                    isd_a[i] = r ? __builtin_amdgcn_rsqf(var_a) : 0.0f;
+                }
+            }
+        }
+
+        // --- per-pixel sweep state -------------------------------------------
+        float c1[R], c2[R], cm[R], cp[R], cprev[R];
+        int kb[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            c1[i] = PSW_INF; c2[i] = PSW_INF; cm[i] = PSW_INF; cp[i] = PSW_INF; cprev[i] = PSW_INF;
+            kb[i] = -1;
+        }
+        const float invT = SOFT ? 1.0f / J.temperature : 0.0f;
+        // soft state reuses c1 (running max of -C/T), c2 (sum exp), cm (sum exp * rho)
+        if (SOFT) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) { c1[i] = -PSW_INF; c2[i] = 0.0f; cm[i] = 0.0f; }
+        }
+
+        const int K = J.best_k;
+        const float invN = 1.0f / (float)(WIN * WIN);
+        const float vfn = J.var_floor_n;
+
+        for (int fam = 0; fam < 2; ++fam) {
+            const int np = fam ? J.n_ground : J.n_fronto;
+            if (np == 0) continue;
+            const int k0 = fam ? J.n_fronto : 0;
+            // family ray parameter: tau where the family's planes are hit in
+            // front of the camera, NaN elsewhere (NaN fails every later test)
+            float tf[NWR];
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < NWR; ++i) {
+                float t = ray_tau(x, yw[i], xi, nullptr);
+                const float g = fam ? fmaf(J.gn[0], x, fmaf(J.gn[1], yw[i], J.gn[2] * t)) : t;
+                const bool ok = g > 0.0f;
+                tf[i] = ok ? t : __builtin_nanf("");
+                any |= ok && (wave + NW * i) < T;
+            }
+            if (!__syncthreads_or(any)) continue;
+#pragma unroll
+            for (int i = 0; i < R; ++i) cprev[i] = PSW_INF;
+
+            for (int kk = 0; kk < np; ++kk) {
+                const int k = k0 + kk;
+                // ---- warp all sources' sample rows of this plane into LDS ----
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const PSW_CONST float *hm = cptr(J.htab) + (k * S + s) * 9;
+                    const float h1x = hm[0], h1y = hm[1], h1z = hm[2];
+                    const float h2x = hm[3], h2y = hm[4], h2z = hm[5];
+                    const float h3x = hm[6], h3y = hm[7], h3z = hm[8];
+                    const float sxi = J.src[s].xi, sfx = J.src[s].fx, sfy = J.src[s].fy;
+                    const float scx = J.src[s].cx, scy = J.src[s].cy;
+                    const float wm1 = J.src[s].wm1, hm1 = J.src[s].hm1;
+                    const uint32_t row_bytes = (uint32_t)J.src[s].w * 4u;
+                    // buffer reads outside the texture return 0, so even the
+                    // address of an invalid sample cannot fault
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        (void *)J.src[s].tex, (short)0, (int)(row_bytes * (uint32_t)J.src[s].h), 0x00020000);
+                    const float px = h1x * x, py = h1y * x, pz = h1z * x;
+                    ST *dst = tile + (size_t)s * T * kWave + lane;
+#pragma unroll
+                    for (int i = 0; i < NWR; ++i) {
+                        const int j = wave + NW * i;
+                        if (i == NWR - 1 && j >= T) break;
+                        const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
+                        const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
+                        const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
+                        const float m = __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z)));
+                        const float den = fmaf(sxi, m, Z);
+                        const float inv = __builtin_amdgcn_rcpf(den);
+                        const float u = fmaf(X * inv, sfx, scx);
+                        const float v = fmaf(Y * inv, sfy, scy);
+                        const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= wm1) & (v >= 0.0f) & (v <= hm1);
+                        const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + ((uint32_t)(int)u << 2);
+                        const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
+                        const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+                        const float p00 = (float)(q & 0xffu), p10 = (float)((q >> 8) & 0xffu);
+                        const float p01 = (float)((q >> 16) & 0xffu), p11 = (float)(q >> 24);
+                        const float top = fmaf(al, p10 - p00, p00);
+                        const float bot = fmaf(al, p11 - p01, p01);
+                        const float b = fmaf(be, bot - top, top - 128.0f);
+                        dst[(size_t)j * kWave] = St::put(ok ? b : -0.0f);
+                    }
+                }
+                __syncthreads();
+
+                // ---- run down the rows: vertical sums, then window sums ----
+                float vb[S], vbb[S], vab[S];
+                int last_bad[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s) { vb[s] = 0.f; vbb[s] = 0.f; vab[s] = 0.f; last_bad[s] = -1000; }
+                const ST *col = tile + (size_t)(wave * R) * kWave + lane;
+#pragma unroll
+                for (int m = 0; m < VR; ++m) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const ST *cs = col + (size_t)s * T * kWave;
+                        const float b = St::get(cs[(size_t)m * kWave]);
+                        last_bad[s] = is_neg_zero(b) ? m : last_bad[s];
+                        vb[s] += b;
+                        vbb[s] = fmaf(b, b, vbb[s]);
+                        vab[s] = fmaf(av[m], b, vab[s]);
+                        if (m >= WIN) {
+                            const float bo = St::get(cs[(size_t)(m - WIN) * kWave]);
+                            vb[s] -= bo;
+                            vbb[s] = fmaf(-bo, bo, vbb[s]);
+                            vab[s] = fmaf(-av[m - WIN], bo, vab[s]);
+                        }
+                    }
+                    if (m >= WIN - 1) {
+                        const int i = m - (WIN - 1);
+                        float cs4[4];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) cs4[s] = PSW_INF;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            const float hb = wsum<WIN>(vb[s], sh);
+                            const float hbb = wsum<WIN>(vbb[s], sh);
+                            const float hab = wsum<WIN>(vab[s], sh);
+                            const uint64_t bm = __builtin_amdgcn_ballot_w64(last_bad[s] > m - WIN);
+                            const bool bad = bm != 0 && __builtin_amdgcn_inverse_ballot_w64(dilate<WIN>(bm));
+                            const float cov = fmaf(-mean_a[i], hb, hab);
+                            const float varb = fmaf(-hb * invN, hb, hbb);
+                            float zn = cov * isd_a[i] * __builtin_amdgcn_rsqf(varb);
+                            zn = __builtin_amdgcn_fmed3f(zn, -1.0f, 1.0f);
+                            const float c = fmaf(-0.5f, zn, 0.5f);
+                            cs4[s] = (!bad && varb > vfn) ? c : PSW_INF;
+                        }
+                        const float C0 = aggregate<S>(cs4, K);
+                        float C = C0;
+                        C = ((ref_ok >> i) & 1u) ? C : PSW_INF;
+                        if (!SOFT) {
+                            const bool nb = C < c1[i];
+                            const bool fill = (kb[i] == k - 1) && (kk > 0);
+                            cp[i] = nb ? PSW_INF : (fill ? C : cp[i]);
+                            c2[i] = nb ? c1[i] : fminf(c2[i], C);
+                            cm[i] = nb ? cprev[i] : cm[i];
+                            kb[i] = nb ? k : kb[i];
+                            c1[i] = nb ? C : c1[i];
+                            cprev[i] = C;
+                        } else if (C < PSW_INF) {
+                            const float l = -C * invT;
+                            const float nm = fmaxf(c1[i], l);
+                            const float ea = __expf(c1[i] - nm), eb = __expf(l - nm);
+                            const float th = cptr(J.theta)[k];
+                            c2[i] = fmaf(c2[i], ea, eb);
+                            cm[i] = fmaf(cm[i], ea, eb * th);
+                            c1[i] = nm;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // --- epilogue --------------------------------------------------------
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (!((pos_ok >> i) & 1u)) continue;
+            const int orow = or0 + i;
+            if (SOFT) {
+                const bool ok = c1[i] > -PSW_INF;
+                const int64_t so = (int64_t)orow * J.soft_pitch + sc;
+                gptr(J.soft_rho)[so] = ok ? cm[i] / c2[i] : __builtin_nanf("");
+                gptr(J.soft_lse)[so] = ok ? c1[i] + __logf(c2[i]) : -PSW_INF;
+                continue;
+            }
+            const int64_t o = (int64_t)orow * J.out_pitch + sc;
+            const int k = kb[i];
+            float dl = 0.0f, depth = __builtin_nanf(""), zz = __builtin_nanf("");
+            if (k >= 0) {
+                if (cm[i] < PSW_INF && cp[i] < PSW_INF) {
+                    const float den = cm[i] - 2.0f * c1[i] + cp[i];
+                    if (den > 0.0f) dl = __builtin_amdgcn_fmed3f((cm[i] - cp[i]) / (2.0f * den), -0.5f, 0.5f);
+                }
+                const bool fr = k < J.n_fronto;
+                const float th = cptr(J.theta)[k] + dl * (fr ? J.step_f : J.step_g);
+                const float y = ((float)orow - J.cy) * J.inv_fy;
+                float eta;
+                const float t = ray_tau(x, y, xi, &eta);
+                const float rz = eta * t;
+                if (fr) {
+                    depth = 1.0f / (th * rz);
+                } else {
+                    const float nr = eta * fmaf(J.gn[0], x, fmaf(J.gn[1], y, J.gn[2] * t));
+                    depth = (J.gd - th) / nr;
+                }
+                zz = depth * rz;
+            }
+            if (J.index) gptr(J.index)[o] = k;
+            if (J.delta) gptr(J.delta)[o] = dl;
+            if (J.cost1) gptr(J.cost1)[o] = c1[i];
+            if (J.cost2) gptr(J.cost2)[o] = k >= 0 ? c2[i] : PSW_INF;
+            if (J.depth) gptr(J.depth)[o] = depth;
+            if (J.z) gptr(J.z)[o] = zz;
+            if (J.level_id) gptr(J.level_id)[o] = k >= 0 ? 0 : 255;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+// One grid per (frame, level): blockIdx.x enumerates tiles; consecutive
+// blocks go to different XCDs, so block b is given tile (b % 8) * per + b / 8
+// and every XCD sweeps a contiguous band of the image (its L2 then holds the
+// band's source texels).
+template <int WIN, int R, int NW, int S, int STORE, bool SOFT>
+__global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__restrict__ job) {
+    extern __shared__ char smem[];
+    const int nt = job->tiles_x * job->tiles_y;
+    const int per = (nt + 7) / 8;
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per + (b >> 3);
+    if (t >= nt) return;
+    Tile<WIN, R, NW, S, STORE, SOFT>::run(job, t % job->tiles_x, t / job->tiles_x, smem);
+}
+
+// One persistent launch for every (frame, level, tile) of a run: workgroups
+// take tiles from a global counter until all are done (every workgroup
+// leaves once the counter passes n_items).
+template <int R, int NW, int S, int STORE>
+__global__ __launch_bounds__(kWave *NW) void sweep_persistent_kernel(const JobDev *__restrict__ jobs, int n_jobs,
+                                                                     int n_items, int *counter) {
+    extern __shared__ char smem[];
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= n_items) break;
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].first_item <= item) ++j;
+        const JobDev *J = jobs + j;
+        const int t = item - J->first_item;
+        const int tx = t % J->tiles_x, ty = t / J->tiles_x;
+        if (J->window == 7) Tile<7, R, NW, S, STORE, false>::run(J, tx, ty, smem);
+        else Tile<9, R, NW, S, STORE, false>::run(J, tx, ty, smem);
+    }
+}
+
+}  // namespace psw

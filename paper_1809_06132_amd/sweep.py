@@ -1,0 +1,211 @@
+"""Torch-facing wrapper of the plane-sweep library.
+
+PyTorch supplies device memory (images, outputs, the workspace) and the HIP
+stream; every step of the sweep runs in libpsweep.so.  Settings objects are
+duck-typed: anything with the attributes of a level (n_fronto, near, far,
+n_ground, h_lo, h_hi, window, downsample, crop) and of the settings (levels,
+best_k, var_floor, ground_n, ground_d, mode, temperature) works."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import psweep as P
+
+_STORAGE = {"f32": P.STORAGE_F32, "f16": P.STORAGE_F16, "bf16": P.STORAGE_BF16}
+_LAUNCH = {"grid": P.LAUNCH_GRID, "persistent": P.LAUNCH_PERSISTENT}
+
+
+def make_config(settings, max_width, max_height, max_sources, max_frames=1, max_camera_sets=1,
+                storage="f32", launch="grid") -> P.psweep_config:
+    c = P.psweep_config()
+    c.n_levels = len(settings.levels)
+    for i, lv in enumerate(settings.levels):
+        L = c.level[i]
+        L.n_fronto, L.near_m, L.far_m = int(lv.n_fronto), float(lv.near), float(lv.far)
+        L.n_ground, L.h_lo, L.h_hi = int(lv.n_ground), float(lv.h_lo), float(lv.h_hi)
+        L.window, L.downsample = int(lv.window), int(lv.downsample)
+        L.crop_x, L.crop_y, L.crop_w, L.crop_h = [int(v) for v in lv.crop]
+    c.ground_n[:] = [float(v) for v in settings.ground_n]
+    c.ground_d = float(settings.ground_d)
+    c.best_k = int(settings.best_k)
+    c.var_floor = float(settings.var_floor)
+    c.storage = _STORAGE[storage]
+    c.mode = P.MODE_SOFT if settings.mode == "soft" else P.MODE_WTA
+    c.temperature = float(settings.temperature)
+    c.launch = _LAUNCH[launch]
+    c.max_width, c.max_height = int(max_width), int(max_height)
+    c.max_sources, c.max_frames, c.max_camera_sets = int(max_sources), int(max_frames), int(max_camera_sets)
+    return c
+
+
+def camera(cam) -> P.psweep_camera:
+    return P.psweep_camera(float(cam.xi), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                           int(cam.width), int(cam.height))
+
+
+def pose(ps) -> P.psweep_pose:
+    o = P.psweep_pose()
+    o.R[:] = [float(v) for v in np.asarray(ps.R, np.float64).ravel()]
+    o.t[:] = [float(v) for v in np.asarray(ps.t, np.float64).ravel()]
+    return o
+
+
+def _stream_handle(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class PlaneSweep:
+    """A context, its workspace and output allocation helpers."""
+
+    def __init__(self, settings, max_width, max_height, max_sources, max_frames=1, max_camera_sets=1,
+                 storage="f32", launch="grid", device="cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("PlaneSweep needs a GPU (the sweep has no CPU path)")
+        self.settings = settings
+        self.device = torch.device(device)
+        self.cfg = make_config(settings, max_width, max_height, max_sources, max_frames, max_camera_sets,
+                               storage, launch)
+        self.ctx = P.psweep_create(self.cfg)
+        n = P.psweep_workspace_size(self.ctx)
+        self.workspace = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        P.psweep_set_workspace(self.ctx, aligned, n)
+        self.cams = {}
+        self._keep = []
+
+    def close(self):
+        if self.ctx is not None:
+            P.psweep_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- configuration ------------------------------------------------------
+    def set_cameras(self, camera_set, ref_cam, src_cams, poses):
+        P.psweep_set_cameras(self.ctx, camera_set, camera(ref_cam), [camera(c) for c in src_cams],
+                             [pose(p) for p in poses])
+        self.cams[camera_set] = (ref_cam, list(src_cams))
+
+    def set_crop(self, camera_set, x, y, w, h):
+        P.psweep_set_crop(self.ctx, camera_set, x, y, w, h)
+
+    def set_tile(self, level, rows_per_wave, waves):
+        P.psweep_set_tile(self.ctx, level, rows_per_wave, waves)
+
+    def set_timing(self, on=True):
+        P.psweep_set_timing(self.ctx, on)
+
+    def sweep_kernel_ms(self):
+        return P.psweep_sweep_kernel_ms(self.ctx)
+
+    # -- buffers ------------------------------------------------------------
+    def alloc_maps(self, h, w, with_level=True):
+        d = self.device
+        return {"depth": torch.empty((h, w), dtype=torch.float32, device=d),
+                "z": torch.empty((h, w), dtype=torch.float32, device=d),
+                "index": torch.empty((h, w), dtype=torch.int32, device=d),
+                "delta": torch.empty((h, w), dtype=torch.float32, device=d),
+                "cost1": torch.empty((h, w), dtype=torch.float32, device=d),
+                "cost2": torch.empty((h, w), dtype=torch.float32, device=d),
+                **({"level": torch.empty((h, w), dtype=torch.uint8, device=d)} if with_level else {})}
+
+    def level_size(self, camera_set, lv_index):
+        ref, _ = self.cams[camera_set]
+        lv = self.settings.levels[lv_index]
+        w, h = ref.width // lv.downsample, ref.height // lv.downsample
+        if lv.crop[2] > 0:
+            w, h = lv.crop[2], lv.crop[3]
+        return h, w
+
+    def alloc_outputs(self, camera_set=0, level_maps=False):
+        ref, _ = self.cams[camera_set]
+        out = {"merged": self.alloc_maps(ref.height, ref.width)}
+        if self.settings.mode == "soft":
+            out["soft_invdepth"] = torch.empty((ref.height, ref.width), dtype=torch.float32, device=self.device)
+            out["soft_lse"] = torch.empty((ref.height, ref.width), dtype=torch.float32, device=self.device)
+        if level_maps:
+            out["levels"] = [self.alloc_maps(*self.level_size(camera_set, l), with_level=False)
+                             for l in range(len(self.settings.levels))]
+        return out
+
+    # -- marshalling --------------------------------------------------------
+    @staticmethod
+    def _maps(m: dict | None) -> P.psweep_maps:
+        pm = P.psweep_maps()
+        if m is None:
+            return pm
+        for key in ("depth", "z", "index", "delta", "cost1", "cost2", "level"):
+            t = m.get(key)
+            if t is not None:
+                assert t.is_cuda and t.is_contiguous()
+                setattr(pm, key, t.data_ptr())
+        pm.pitch = 0
+        return pm
+
+    def _frame(self, fr: dict) -> P.psweep_frame:
+        f = P.psweep_frame()
+        ref = fr["ref"]
+        assert ref.dtype == torch.uint8 and ref.is_cuda and ref.dim() == 2 and ref.stride(1) == 1
+        f.ref, f.ref_pitch = ref.data_ptr(), ref.stride(0)
+        for s, img in enumerate(fr["srcs"]):
+            assert img.dtype == torch.uint8 and img.is_cuda and img.dim() == 2 and img.stride(1) == 1
+            f.src[s], f.src_pitch[s] = img.data_ptr(), img.stride(0)
+        f.camera_set = int(fr.get("camera_set", 0))
+        return f
+
+    def _output(self, o: dict) -> P.psweep_output:
+        po = P.psweep_output()
+        po.merged = self._maps(o.get("merged"))
+        for l, m in enumerate(o.get("levels", []) or []):
+            po.level[l] = self._maps(m)
+        if "soft_invdepth" in o:
+            po.soft_invdepth = o["soft_invdepth"].data_ptr()
+            po.soft_lse = o["soft_lse"].data_ptr()
+        return po
+
+    # -- run ----------------------------------------------------------------
+    def run(self, frames, outputs, stream=None):
+        """Enqueue one run of the whole sweep for `frames` (list of dicts with
+        'ref', 'srcs', 'camera_set') into `outputs` (list of dicts from
+        alloc_outputs)."""
+        pf = [self._frame(f) for f in frames]
+        po = [self._output(o) for o in outputs]
+        P.psweep_run(self.ctx, pf, po, _stream_handle(stream))
+
+    def capture_graph(self, frames, outputs, stream=None):
+        pf = [self._frame(f) for f in frames]
+        po = [self._output(o) for o in outputs]
+        self._keep = [frames, outputs]
+        P.psweep_graph_capture(self.ctx, pf, po, _stream_handle(stream))
+
+    def launch_graph(self, stream=None):
+        P.psweep_graph_launch(self.ctx, _stream_handle(stream))
+
+    def plane_pixels(self, frames) -> int:
+        return P.psweep_plane_pixels(self.ctx, [self._frame(f) for f in frames])
+
+    def soft_backward(self, grad_invdepth, src_shapes, stream=None):
+        """Gradients of sum(grad * soft_invdepth) of the last soft run: list of
+        per-source image gradients and a [S, 6] float64 pose gradient (v, omega)."""
+        g = grad_invdepth.contiguous().float()
+        gs = [torch.empty(s, dtype=torch.float32, device=self.device) for s in src_shapes]
+        gp = torch.empty((len(src_shapes), 6), dtype=torch.float64, device=self.device)
+        P.psweep_soft_depth_backward(self.ctx, g.data_ptr(), [t.data_ptr() for t in gs], gp.data_ptr(),
+                                     _stream_handle(stream))
+        return gs, gp
+
+
+def frame_to_device(frame, device="cuda:0"):
+    """Upload a scenegen-style frame (numpy uint8 images) to the GPU."""
+    return {"ref": torch.from_numpy(np.ascontiguousarray(frame.ref)).to(device),
+            "srcs": [torch.from_numpy(np.ascontiguousarray(s)).to(device) for s in frame.srcs],
+            "camera_set": 0}

@@ -1,0 +1,80 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and rejects bad configurations on the host before touching a GPU."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "psweep.h")
+
+
+def _lib_or_skip():
+    from paper_1809_06132_amd import psweep
+    if not os.path.exists(psweep.LIB_PATH):
+        pytest.skip("libpsweep.so not built (run __graft_entry__.build())")
+    return psweep
+
+
+def test_header_and_binding_agree():
+    decl = set(re.findall(r"\b(psweep_[a-z_]+)\s*\(", open(HEADER).read()))
+    from paper_1809_06132_amd import psweep
+    assert decl == set(psweep.EXPORTS), decl ^ set(psweep.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    psweep = _lib_or_skip()
+    L = psweep.lib()
+    for name in psweep.EXPORTS:
+        assert hasattr(L, name), name
+    assert psweep.psweep_version().startswith("psweep-gfx950")
+
+
+def _cfg(psweep, **kw):
+    c = psweep.psweep_config()
+    c.n_levels = 1
+    L = c.level[0]
+    L.n_fronto, L.near_m, L.far_m, L.window, L.downsample = 32, 0.5, 30.0, 7, 1
+    c.ground_n[:] = [0.0, 1.0, 0.0]
+    c.ground_d = 1.5
+    c.best_k, c.var_floor, c.temperature = 1, 1.0, 0.1
+    c.max_width, c.max_height, c.max_sources, c.max_frames, c.max_camera_sets = 320, 256, 1, 1, 1
+    for k, v in kw.items():
+        if "." in k:
+            a, b = k.split(".")
+            setattr(c.level[int(a)], b, v)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw,status", [
+    ({"0.window": 8}, -1),                # even window
+    ({"0.window": 17}, -1),               # too large
+    ({"0.n_fronto": 1}, -1),              # a family needs 2 planes
+    ({"0.near_m": 40.0}, -1),             # near beyond far
+    ({"best_k": 2}, -1),                  # more than max_sources
+    ({"max_sources": 5}, -1),
+    ({"n_levels": 3}, -1),
+    ({"storage": 7}, -1),
+    ({"0.n_ground": 4, "0.h_lo": -0.5, "0.h_hi": 0.5, "ground_d": 0.2}, -1),  # planes above the camera
+    ({"mode": 1, "0.n_ground": 4, "0.h_lo": -0.5, "0.h_hi": 0.5}, -5),      # soft with ground planes
+    ({"mode": 1, "launch": 1}, -5),
+    ({"launch": 1, "0.window": 5}, -5),
+    ({"0.crop_w": 100, "0.crop_h": 100}, -5),
+])
+def test_create_rejects_bad_config(kw, status):
+    psweep = _lib_or_skip()
+    with pytest.raises(psweep.PsweepError) as ei:
+        psweep.psweep_create(_cfg(psweep, **kw))
+    assert ei.value.status == status
+    assert psweep.psweep_last_error(None)
+
+
+def test_null_arguments():
+    psweep = _lib_or_skip()
+    L = psweep.lib()
+    assert L.psweep_create(None, None) == psweep.EINVAL
+    assert L.psweep_workspace_size(None, None) == psweep.EINVAL
+    assert L.psweep_run(None, None, 0, None, None) == psweep.EINVAL
+    assert L.psweep_soft_depth_backward(None, None, None, None, None) == psweep.EINVAL
