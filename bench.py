@@ -1,0 +1,139 @@
+"""Throughput of the fisheye plane sweep on one MI355X.
+
+A step is one whole pass of the hot path (level images, border marks, the
+sweep, the epilogue) over one frame of the workload: the 1024x768 street
+scene with 3 sources, 128 fronto + 64 ground planes, 9x9 ZNCC, mean of the
+best 2 sources, winner-take-all with parabolic refinement, FP32.  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line: plane-pixel evaluations per second (pixels x planes per
+step / step time), the roofline of the sweep kernel (VALU-bound; achieved
+algorithmic lane-ops per second over the chip's non-packed FP32 issue rate,
+from the kernel's own HIP-event durations), and the FP64 CPU oracle timed on
+a bounded sample of the same workload."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "plane-pixel evals/s (Gpix·planes/s) + depth maps/s vs plain FP32, 1 GPU"
+# non-packed FP32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def algorithmic_ops_per_plane_pixel(n_src: int) -> int:
+    """Lane-ops of the method's own arithmetic per (pixel, plane): per source
+    9 (plane-induced point) + 10 (projection) + 5 (bounds) + 10 (bilinear) +
+    1 (centring) + 14 (window sums) + 9 (ZNCC and cost) + 2 (aggregation),
+    and 6 for the winner-take-all update."""
+    return 60 * n_src + 6
+
+
+def cpu_baseline(fr, st, target_s=15.0):
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(99)
+    lv = st.levels[0]
+    P = lv.n_fronto + lv.n_ground
+
+    def sample(n):
+        return np.stack([rng.integers(0, fr.ref.shape[1], n), rng.integers(0, fr.ref.shape[0], n)], 1).astype(np.int32)
+
+    n = 1024
+    t0 = time.perf_counter()
+    oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=sample(n))
+    dt = time.perf_counter() - t0
+    n2 = int(min(2_000_000, max(1024, n * (target_s - dt) / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=sample(n2))
+    dt2 = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n2 * P / dt2 / 1e9, "unit": "Gpix·planes/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n2} random pixels of the 1024x768 frame, all {P} planes x 3 sources, "
+                      f"FP64 two-pass ZNCC per window ({dt2:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build sweeps on one "
+              "device; see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import scenegen
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+
+    wl = scenegen.workload("C2")
+    fr, st = wl.frames[0], wl.settings
+    ps = PlaneSweep(st, fr.ref_cam.width, fr.ref_cam.height, len(fr.srcs), storage=args.storage)
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    frame = frame_to_device(fr)
+    out = ps.alloc_outputs()
+    plane_pixels = ps.plane_pixels([frame])
+    for _ in range(args.warmup):
+        ps.run([frame], [out])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ps.run([frame], [out])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = elapsed / args.steps * 1e3
+
+    # sweep-kernel duration from HIP events recorded on the launch stream
+    ps.set_timing(True)
+    kms = []
+    for _ in range(max(5, min(20, args.steps))):
+        ps.run([frame], [out])
+        torch.cuda.synchronize()
+        kms.append(ps.sweep_kernel_ms()[0])
+    ps.set_timing(False)
+    kernel_ms = sorted(kms)[len(kms) // 2]
+    ops = plane_pixels * algorithmic_ops_per_plane_pixel(len(fr.srcs))
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    line = {
+        "metric": METRIC,
+        "value": plane_pixels / (ms * 1e-3) / 1e9,
+        "unit": "Gpix·planes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "maps_per_s": 1e3 / ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "f32" else f"{args.storage}-staged/f32",
+        "data": "synthetic (seeded ray-cast street scene)",
+        "config": {"workload": "C2: 1024x768 ref + 3 fisheye sources (xi 0.9), 128 fronto + 64 ground planes, "
+                               "ZNCC 9x9, mean of best 2, WTA + parabola",
+                   "plane_pixels_per_step": plane_pixels, "launch": "grid", "storage": args.storage},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-ops/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel_ms": kernel_ms,
+                     "ops_per_plane_pixel": algorithmic_ops_per_plane_pixel(len(fr.srcs))},
+    }
+    ps.close()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(fr, st)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

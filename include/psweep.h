@@ -189,7 +189,8 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
  * v, omega; overwritten).  Uses the images and soft outputs of the last
  * psweep_run, which must have been a soft run (ESTATE otherwise).  Warps are
  * recomputed, not stored.  Image gradients are accumulated with atomics, so
- * they vary in the last bits from run to run. */
+ * they vary in the last bits from run to run.  Windows 5, 7, 9 and up to three
+ * sources (EUNSUPPORTED otherwise). */
 psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_invdepth,
                                          float *const *d_grad_src, double *d_grad_pose, void *hip_stream);
 
@@ -216,6 +217,11 @@ psweep_status psweep_set_timing(psweep_ctx *ctx, int32_t on);
  * after the stream has been synchronised by the caller).  ESTATE if no run
  * recorded events. */
 psweep_status psweep_sweep_kernel_ms(psweep_ctx *ctx, double *ms, int32_t *n_launches);
+
+/* Durations in milliseconds of each sweep kernel launch of the last run, in
+ * launch order (one per (frame, level) with the grid launch, one for the
+ * persistent launch); at most `capacity` values, *n receives the count. */
+psweep_status psweep_sweep_kernel_times(psweep_ctx *ctx, double *ms, int32_t capacity, int32_t *n);
 
 /* Plane-pixel evaluations (pixels x planes, all levels, all frames) of one
  * psweep_run with these frames, for throughput accounting. */

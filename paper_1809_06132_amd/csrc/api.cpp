@@ -749,6 +749,20 @@ psweep_status psweep_sweep_kernel_ms(psweep_ctx *ctx, double *ms, int32_t *n_lau
     return PSWEEP_OK;
 }
 
+psweep_status psweep_sweep_kernel_times(psweep_ctx *ctx, double *ms, int32_t capacity, int32_t *n) {
+    if (!ctx || !ms || !n || capacity < 0) return PSWEEP_EINVAL;
+    if (ctx->n_timed == 0) return fail(ctx, PSWEEP_ESTATE, "no timed sweep launches (enable timing first)");
+    const int m = std::min(capacity, ctx->n_timed);
+    for (int i = 0; i < m; ++i) {
+        float t = 0;
+        hipError_t e = hipEventElapsedTime(&t, ctx->ev0[i], ctx->ev1[i]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "event elapsed");
+        ms[i] = t;
+    }
+    *n = ctx->n_timed;
+    return PSWEEP_OK;
+}
+
 psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
                                    const psweep_output *out, void *hip_stream) {
     if (!ctx) return PSWEEP_EINVAL;
@@ -814,6 +828,7 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     const void *bk = psw_backward_kernel(win, C.n_src);
     if (!bk) return fail(ctx, PSWEEP_EUNSUPPORTED, "no backward kernel for this window / source count");
     const size_t lds = psw_backward_lds(win, C.n_src);
+    if (lds > 65536) PSW_HIP(hipFuncSetAttribute(bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds limit");
     const int hw = win / 2;
     const int w = C.ref.width, h = C.ref.height;
     const int tx = (w - 2 * hw + (kWave - 2 * hw) - 1) / (kWave - 2 * hw);

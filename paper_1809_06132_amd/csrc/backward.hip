@@ -1,5 +1,25 @@
-// Soft-argmin backward pass (gradient with respect to the source images and
-// the source poses).
+// Soft-argmin backward pass: gradient of L = sum_p g_p rho_hat_p with respect
+// to every source image and every source pose (left perturbation
+// X_s -> X_s + v + omega x X_s).
+//
+// Chain per (pixel p, plane k, source s), recomputed from scratch (nothing of
+// the forward cost volume is stored):
+//   rho_hat = sum_k p_k theta_k, p = softmax(-C / T):
+//       dL/dC_k = g_p * (-1/T) * p_k * (theta_k - rho_hat_p)
+//   C_k = mean of the best K' source costs:   dC/dc_s = 1/K' (chosen s)
+//   c_s = (1 - Z) / 2:                        dc/dZ = -1/2
+//   Z = sum (a-abar)(b-bbar) / sqrt(s_aa s_bb):
+//       dZ/db_q = (a_q - abar)/D - Z (b_q - bbar)/s_bb   for q in the window
+// so that, with G = dL/dZ per window, the gradient at sample q is a window
+// (transposed box) sum over the pixels whose window holds q:
+//   dL/db_q = a_q sum(G/D) - sum(G abar/D) - b_q sum(G Z/s_bb) + sum(G Z bbar/s_bb).
+// Each sample's gradient then goes through the bilinear interpolant to the
+// four source texels (atomics) and through the projection to the pose.
+//
+// Tile layout as in the forward sweep: 4 waves, lane = sample column, 8 output
+// rows per wave; per plane the warped rows go to LDS, the four channels of
+// every output pixel go to LDS, and every wave then handles its own sample
+// rows (interleaved across waves, as in the warp phase).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -12,10 +32,331 @@ __global__ void zero_kernel(float *p, int64_t n) {
         p[i] = 0.0f;
 }
 
+template <int WIN, int S>
+struct Backward {
+    static constexpr int NW = 4, R = 8;
+    static constexpr int HW = WIN / 2;
+    static constexpr int TXO = kWave - 2 * HW;
+    static constexpr int TYO = NW * R;
+    static constexpr int T = TYO + 2 * HW;
+    static constexpr int NWR = (T + NW - 1) / NW;
+    static constexpr int VR = R + 2 * HW;
+    static constexpr int NCH = 4;
+
+    static constexpr size_t lds_tile() { return (size_t)S * T * kWave * 4; }
+    static constexpr size_t lds_bytes() { return lds_tile() + (size_t)NCH * S * TYO * kWave * 4; }
+
+    __device__ static void run(const JobDev *__restrict__ Jp, const float *__restrict__ gin,
+                               const float *__restrict__ rho_hat, const float *__restrict__ lse, int64_t spitch,
+                               float *const gsrc[4], double *__restrict__ gpose, char *smem) {
+        const JobDev &J = *Jp;
+        float *tile = reinterpret_cast<float *>(smem);
+        float *chan = tile + (size_t)S * T * kWave;   // [s][c][output row][lane]
+        const int lane = threadIdx.x & (kWave - 1);
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        const int W = J.w, H = J.h;
+        const int sc = blockIdx.x * TXO + lane;
+        const int sr0 = blockIdx.y * TYO;
+        const int or0 = sr0 + wave * R + HW;
+        const float xi = J.xi;
+        const float x = ((float)sc - J.cx) * J.inv_fx;
+        const float invT = 1.0f / J.temperature;
+        const float invN = 1.0f / (float)(WIN * WIN);
+        Shifts sh;
+        sh.init(lane);
+
+        // sample rows this wave warps (and later scatters)
+        float yw[NWR], tf[NWR], aw[NWR];
+#pragma unroll
+        for (int i = 0; i < NWR; ++i) {
+            const int v = sr0 + wave + NW * i;
+            yw[i] = ((float)v - J.cy) * J.inv_fy;
+            const float t = ray_tau(x, yw[i], xi, nullptr);
+            tf[i] = t > 0.0f ? t : __builtin_nanf("");
+            aw[i] = (sc < W && v < H) ? (float)gptr(J.ref)[(int64_t)v * J.ref_pitch + sc] - 128.0f : 0.0f;
+        }
+        // rows this wave runs down (forward recompute of the window sums)
+        float av[VR];
+#pragma unroll
+        for (int m = 0; m < VR; ++m) {
+            const int v = sr0 + wave * R + m;
+            av[m] = (sc < W && v < H) ? (float)gptr(J.ref)[(int64_t)v * J.ref_pitch + sc] - 128.0f : 0.0f;
+        }
+        float mean_a[R], isd_a[R], gp[R], rh[R], ls[R];
+        uint32_t ref_ok = 0;
+        {
+            const float N = (float)(WIN * WIN);
+            int va = 0, vaa = 0;
+#pragma unroll
+            for (int m = 0; m < VR; ++m) {
+                const int a = (int)av[m];
+                va += a; vaa += a * a;
+                if (m >= WIN) { const int ao = (int)av[m - WIN]; va -= ao; vaa -= ao * ao; }
+                if (m >= WIN - 1) {
+                    const int i = m - (WIN - 1);
+                    const int sa = wsum_i<WIN>(va, sh), saa = wsum_i<WIN>(vaa, sh);
+                    const float var_a = (float)(WIN * WIN * saa - sa * sa) / N;
+                    const int orow = or0 + i;
+                    const bool p = lane >= HW && lane < kWave - HW && sc <= W - 1 - HW && orow <= H - 1 - HW;
+                    float g = 0.f, r = 0.f, l = -__builtin_huge_valf();
+                    if (p) {
+                        const int64_t so = (int64_t)orow * spitch + sc;
+                        g = gin[so]; r = rho_hat[so]; l = lse[so];
+                    }
+                    const bool ok = p && var_a > J.var_floor_n && g != 0.0f && l > -__builtin_huge_valf() &&
+                                    !__builtin_isnan(r);
+                    ref_ok |= (ok ? 1u : 0u) << i;
+                    mean_a[i] = (float)sa / N;
+                    isd_a[i] = ok ? __builtin_amdgcn_rsqf(var_a) : 0.0f;
+                    gp[i] = g; rh[i] = r; ls[i] = l;
+                }
+            }
+        }
+        double acc[S][6];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) acc[s][a] = 0.0;
+        const int K = J.best_k;
+
+        for (int k = 0; k < J.n_fronto; ++k) {
+            const float theta = cptr(J.theta)[k];
+            // ---- forward recompute: warped rows of every source into LDS ----
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const PSW_CONST float *hm = cptr(J.htab) + (k * S + s) * 9;
+                const float h1x = hm[0], h1y = hm[1], h1z = hm[2], h2x = hm[3], h2y = hm[4], h2z = hm[5];
+                const float h3x = hm[6], h3y = hm[7], h3z = hm[8];
+                const SrcDev &sd = J.src[s];
+                const uint32_t row_bytes = (uint32_t)sd.w * 4u;
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)sd.tex, (short)0, (int)(row_bytes * (uint32_t)sd.h), 0x00020000);
+                const float px = h1x * x, py = h1y * x, pz = h1z * x;
+#pragma unroll
+                for (int i = 0; i < NWR; ++i) {
+                    const int j = wave + NW * i;
+                    if (i == NWR - 1 && j >= T) break;
+                    const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
+                    const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
+                    const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
+                    const float m = __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z)));
+                    const float den = fmaf(sd.xi, m, Z);
+                    const float inv = __builtin_amdgcn_rcpf(den);
+                    const float u = fmaf(X * inv, sd.fx, sd.cx);
+                    const float v = fmaf(Y * inv, sd.fy, sd.cy);
+                    const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= sd.wm1) & (v >= 0.0f) & (v <= sd.hm1);
+                    const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + ((uint32_t)(int)u << 2);
+                    const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
+                    const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+                    const float p00 = (float)(q & 0xffu), p10 = (float)((q >> 8) & 0xffu);
+                    const float p01 = (float)((q >> 16) & 0xffu), p11 = (float)(q >> 24);
+                    const float top = fmaf(al, p10 - p00, p00), bot = fmaf(al, p11 - p01, p01);
+                    tile[((size_t)s * T + j) * kWave + lane] = ok ? fmaf(be, bot - top, top - 128.0f) : -0.0f;
+                }
+            }
+            __syncthreads();
+
+            // ---- per output pixel: costs, softmax weight, window channels ----
+            {
+                float vb[S], vbb[S], vab[S];
+                int last_bad[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s) { vb[s] = 0.f; vbb[s] = 0.f; vab[s] = 0.f; last_bad[s] = -1000; }
+#pragma unroll
+                for (int m = 0; m < VR; ++m) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const float *cs = tile + ((size_t)s * T + wave * R) * kWave + lane;
+                        const float b = cs[(size_t)m * kWave];
+                        last_bad[s] = is_neg_zero(b) ? m : last_bad[s];
+                        vb[s] += b; vbb[s] = fmaf(b, b, vbb[s]); vab[s] = fmaf(av[m], b, vab[s]);
+                        if (m >= WIN) {
+                            const float bo = cs[(size_t)(m - WIN) * kWave];
+                            vb[s] -= bo; vbb[s] = fmaf(-bo, bo, vbb[s]); vab[s] = fmaf(-av[m - WIN], bo, vab[s]);
+                        }
+                    }
+                    if (m >= WIN - 1) {
+                        const int i = m - (WIN - 1);
+                        float c4[4] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(),
+                                       __builtin_huge_valf()};
+                        float zs[S], rsb[S], hbs[S];
+#pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            const float hb = wsum<WIN>(vb[s], sh), hbb = wsum<WIN>(vbb[s], sh);
+                            const float hab = wsum<WIN>(vab[s], sh);
+                            const uint64_t bm = __builtin_amdgcn_ballot_w64(last_bad[s] > m - WIN);
+                            const bool bad = bm != 0 && __builtin_amdgcn_inverse_ballot_w64(dilate<WIN>(bm));
+                            const float cov = fmaf(-mean_a[i], hb, hab);
+                            const float varb = fmaf(-hb * invN, hb, hbb);
+                            const float rv = __builtin_amdgcn_rsqf(varb);
+                            const float zn = cov * isd_a[i] * rv;
+                            const float c = fmaf(-0.5f, __builtin_amdgcn_fmed3f(zn, -1.0f, 1.0f), 0.5f);
+                            c4[s] = (!bad && varb > J.var_floor_n) ? c : __builtin_huge_valf();
+                            zs[s] = zn; rsb[s] = rv; hbs[s] = hb;
+                        }
+                        const float C = aggregate<S>(c4, K);
+                        const bool live = ((ref_ok >> i) & 1u) && C < __builtin_huge_valf();
+                        // dL/dC_k, then the share of every chosen source
+                        float dC = 0.0f;
+                        if (live) {
+                            const float pk = __expf(-C * invT - ls[i]);
+                            dC = gp[i] * (-invT) * pk * (theta - rh[i]);
+                        }
+                        int nvalid = 0;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) nvalid += c4[s] < __builtin_huge_valf() ? 1 : 0;
+                        const int kk = K < nvalid ? K : nvalid;
+#pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            int rank = 0;
+#pragma unroll
+                            for (int t = 0; t < S; ++t)
+                                rank += (c4[t] < c4[s] || (c4[t] == c4[s] && t < s)) ? 1 : 0;
+                            const bool chosen = live && c4[s] < __builtin_huge_valf() && rank < kk &&
+                                                __builtin_fabsf(zs[s]) < 1.0f;
+                            const float G = chosen ? -0.5f * dC / (float)kk : 0.0f;   // dL/dZ
+                            const float invD = isd_a[i] * rsb[s];
+                            const float varb_inv = rsb[s] * rsb[s];
+                            const float bbar = hbs[s] * invN;
+                            float *ch = chan + (((size_t)s * NCH) * TYO + wave * R + i) * kWave + lane;
+                            ch[0] = G * invD;
+                            ch[(size_t)TYO * kWave] = G * mean_a[i] * invD;
+                            ch[(size_t)2 * TYO * kWave] = G * zs[s] * varb_inv;
+                            ch[(size_t)3 * TYO * kWave] = G * zs[s] * bbar * varb_inv;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+
+            // ---- transposed window sums at every sample, then scatter ----
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const PSW_CONST float *hm = cptr(J.htab) + (k * S + s) * 9;
+                const float h1x = hm[0], h1y = hm[1], h1z = hm[2], h2x = hm[3], h2y = hm[4], h2z = hm[5];
+                const float h3x = hm[6], h3y = hm[7], h3z = hm[8];
+                const SrcDev &sd = J.src[s];
+                const uint32_t row_bytes = (uint32_t)sd.w * 4u;
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)sd.tex, (short)0, (int)(row_bytes * (uint32_t)sd.h), 0x00020000);
+                const float px = h1x * x, py = h1y * x, pz = h1z * x;
+                float *gimg = gsrc[s];
+#pragma unroll
+                for (int i = 0; i < NWR; ++i) {
+                    const int j = wave + NW * i;
+                    if (i == NWR - 1 && j >= T) break;
+                    // output rows whose window holds sample row j: [j - 2 HW, j]
+                    float sA = 0.f, sB = 0.f, sC = 0.f, sE = 0.f;
+                    const int lo = j - 2 * HW < 0 ? 0 : j - 2 * HW;
+                    const int hi = j < TYO - 1 ? j : TYO - 1;
+                    for (int r = lo; r <= hi; ++r) {
+                        const float *ch = chan + (((size_t)s * NCH) * TYO + r) * kWave + lane;
+                        sA += ch[0]; sB += ch[(size_t)TYO * kWave];
+                        sC += ch[(size_t)2 * TYO * kWave]; sE += ch[(size_t)3 * TYO * kWave];
+                    }
+                    sA = wsum<WIN>(sA, sh); sB = wsum<WIN>(sB, sh);
+                    sC = wsum<WIN>(sC, sh); sE = wsum<WIN>(sE, sh);
+                    const float b = tile[((size_t)s * T + j) * kWave + lane];
+                    const float gb = fmaf(aw[i], sA, -sB) + fmaf(-b, sC, sE);
+                    if (gb == 0.0f || is_neg_zero(b)) continue;
+                    // recompute the warp of this sample with its derivatives
+                    const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
+                    const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
+                    const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
+                    const float m = __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z)));
+                    const float den = fmaf(sd.xi, m, Z);
+                    const float inv = __builtin_amdgcn_rcpf(den);
+                    const float u = fmaf(X * inv, sd.fx, sd.cx);
+                    const float v = fmaf(Y * inv, sd.fy, sd.cy);
+                    const int i0 = (int)u, j0 = (int)v;
+                    const int i1 = i0 + 1 < sd.w ? i0 + 1 : sd.w - 1;
+                    const int j1 = j0 + 1 < sd.h ? j0 + 1 : sd.h - 1;
+                    const float al = u - (float)i0, be = v - (float)j0;
+                    const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(
+                        rs, (int)(__umul24((uint32_t)j0, row_bytes) + ((uint32_t)i0 << 2)), 0, 0);
+                    const float p00 = (float)(q & 0xffu), p10 = (float)((q >> 8) & 0xffu);
+                    const float p01 = (float)((q >> 16) & 0xffu), p11 = (float)(q >> 24);
+                    float *gi = gimg;
+                    atomicAdd(gi + (int64_t)j0 * sd.w + i0, gb * (1.0f - al) * (1.0f - be));
+                    atomicAdd(gi + (int64_t)j0 * sd.w + i1, gb * al * (1.0f - be));
+                    atomicAdd(gi + (int64_t)j1 * sd.w + i0, gb * (1.0f - al) * be);
+                    atomicAdd(gi + (int64_t)j1 * sd.w + i1, gb * al * be);
+                    const float dbu = fmaf(be, p11 - p01, (1.0f - be) * (p10 - p00));
+                    const float dbv = fmaf(al, p11 - p10, (1.0f - al) * (p01 - p00));
+                    // (X, Y, Z) = H (x, y, tau) is the source point divided by
+                    // sigma = d / (n . r~) = 1 / (theta * tau) for fronto planes
+                    const float sigma = 1.0f / (theta * tf[i]);
+                    const float im = 1.0f / m;
+                    const float dd0 = sd.xi * X * im, dd1 = sd.xi * Y * im, dd2 = fmaf(sd.xi * Z, im, 1.0f);
+                    const float iu = sd.fx * inv, iv = sd.fy * inv;
+                    const float xu = X * inv, yv = Y * inv;
+                    // d(u, v)/d(point), point = sigma (X, Y, Z)
+                    const float du0 = iu * (1.0f - xu * dd0), du1 = -iu * xu * dd1, du2 = -iu * xu * dd2;
+                    const float dv0 = -iv * yv * dd0, dv1 = iv * (1.0f - yv * dd1), dv2 = -iv * yv * dd2;
+                    const float gs = gb / sigma;
+                    const float g0 = gs * fmaf(dbu, du0, dbv * dv0);
+                    const float g1 = gs * fmaf(dbu, du1, dbv * dv1);
+                    const float g2 = gs * fmaf(dbu, du2, dbv * dv2);
+                    const float P0 = sigma * X, P1 = sigma * Y, P2 = sigma * Z;
+                    acc[s][0] += (double)g0;
+                    acc[s][1] += (double)g1;
+                    acc[s][2] += (double)g2;
+                    acc[s][3] += (double)(P1 * g2 - P2 * g1);
+                    acc[s][4] += (double)(P2 * g0 - P0 * g2);
+                    acc[s][5] += (double)(P0 * g1 - P1 * g0);
+                }
+            }
+            __syncthreads();
+        }
+        // ---- pose gradient: wave reduction, one FP64 atomic per wave ----
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                double v = acc[s][a];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+                if (lane == 0 && v != 0.0) atomicAdd(gpose + s * 6 + a, v);
+            }
+    }
+};
+
+template <int WIN, int S>
+__global__ __launch_bounds__(256) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
+                                                        const float *__restrict__ rho, const float *__restrict__ lse,
+                                                        int64_t spitch, float *g0, float *g1, float *g2, float *g3,
+                                                        double *gpose) {
+    extern __shared__ char smem[];
+    float *gs[4] = {g0, g1, g2, g3};
+    Backward<WIN, S>::run(job, gin, rho, lse, spitch, gs, gpose, smem);
+}
+
 }  // namespace psw
 
 extern "C" {
 const void *psw_zero_kernel() { return (const void *)&psw::zero_kernel; }
-const void *psw_backward_kernel(int, int) { return nullptr; }
-size_t psw_backward_lds(int, int) { return 0; }
+
+const void *psw_backward_kernel(int win, int n_src) {
+#define PSW_B(W)                                                            \
+    if (win == W) {                                                         \
+        if (n_src == 1) return (const void *)&psw::backward_kernel<W, 1>; \
+        if (n_src == 2) return (const void *)&psw::backward_kernel<W, 2>; \
+        if (n_src == 3) return (const void *)&psw::backward_kernel<W, 3>; \
+    }
+    PSW_B(5) PSW_B(7) PSW_B(9)
+#undef PSW_B
+    return nullptr;
+}
+
+size_t psw_backward_lds(int win, int n_src) {
+#define PSW_L(W)                                                       \
+    if (win == W) {                                                    \
+        if (n_src == 1) return psw::Backward<W, 1>::lds_bytes();       \
+        if (n_src == 2) return psw::Backward<W, 2>::lds_bytes();       \
+        if (n_src == 3) return psw::Backward<W, 3>::lds_bytes();       \
+    }
+    PSW_L(5) PSW_L(7) PSW_L(9)
+#undef PSW_L
+    return 0;
+}
 }

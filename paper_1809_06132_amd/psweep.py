@@ -25,6 +25,7 @@ _d, _i32, _i64, _p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_v
 EXPORTS = ["psweep_create", "psweep_workspace_size", "psweep_set_workspace", "psweep_set_cameras",
            "psweep_set_crop", "psweep_run", "psweep_soft_depth_backward", "psweep_set_tile",
            "psweep_graph_capture", "psweep_graph_launch", "psweep_set_timing", "psweep_sweep_kernel_ms",
+           "psweep_sweep_kernel_times",
            "psweep_plane_pixels", "psweep_destroy", "psweep_last_error", "psweep_version"]
 
 
@@ -90,6 +91,7 @@ def lib() -> ctypes.CDLL:
     L.psweep_graph_launch.argtypes = [_p, _p]
     L.psweep_set_timing.argtypes = [_p, _i32]
     L.psweep_sweep_kernel_ms.argtypes = [_p, P(_d), P(_i32)]
+    L.psweep_sweep_kernel_times.argtypes = [_p, P(_d), _i32, P(_i32)]
     L.psweep_plane_pixels.argtypes = [_p, P(psweep_frame), _i32, P(_i64)]
     L.psweep_destroy.argtypes = [_p]
     L.psweep_destroy.restype = None
@@ -178,6 +180,13 @@ def psweep_sweep_kernel_ms(ctx):
     ms, n = _d(), _i32()
     _check(lib().psweep_sweep_kernel_ms(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx)
     return ms.value, n.value
+
+
+def psweep_sweep_kernel_times(ctx, capacity: int = 64):
+    arr = (_d * capacity)()
+    n = _i32()
+    _check(lib().psweep_sweep_kernel_times(ctx, arr, capacity, ctypes.byref(n)), ctx)
+    return list(arr[:min(n.value, capacity)])
 
 
 def psweep_plane_pixels(ctx, frames) -> int:
