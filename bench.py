@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build sweeps on one "
@@ -130,6 +132,12 @@ def main():
                      "ops_per_plane_pixel": algorithmic_ops_per_plane_pixel(len(fr.srcs))},
     }
     ps.close()
+    if args.copy_calibration:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(fr, st)
     print(json.dumps(line), flush=True)

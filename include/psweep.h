@@ -201,7 +201,8 @@ psweep_status psweep_set_tile(psweep_ctx *ctx, int32_t level, int32_t rows_per_w
 
 /* Capture one psweep_run of these frames into a HIP graph owned by the
  * context (replacing any earlier graph).  The frame and output pointers are
- * baked in.  Capture happens on hip_stream, which must not be capturing. */
+ * baked in.  The capture runs on a stream of the context's own after a device
+ * synchronisation (hip_stream is unused and may be NULL); this call blocks. */
 psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
                                    const psweep_output *out, void *hip_stream);
 

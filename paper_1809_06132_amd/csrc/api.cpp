@@ -124,9 +124,11 @@ struct psweep_ctx {
     float *soft_rho = nullptr, *soft_lse = nullptr;
     int64_t soft_pitch = 0;
     size_t soft_job_off = 0;   // device address of the job used by the backward
-    // graph
+    // graph (captured on a stream of the context's own: the default stream
+    // cannot be captured)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipStream_t capture_stream = nullptr;
     std::string err;
 };
 
@@ -770,7 +772,12 @@ psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, 
     if (!frames || !out || n_frames < 1 || n_frames > ctx->cfg.max_frames)
         return fail(ctx, PSWEEP_EINVAL, "bad frames");
     if (ctx->cfg.mode == PSWEEP_MODE_SOFT) return fail(ctx, PSWEEP_EUNSUPPORTED, "graphs are for the WTA sweep");
-    hipStream_t stream = (hipStream_t)hip_stream;
+    (void)hip_stream;
+    if (!ctx->capture_stream)
+        PSW_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "capture stream");
+    hipStream_t stream = ctx->capture_stream;
+    // work already enqueued by the caller must finish before the tables change
+    PSW_HIP(hipDeviceSynchronize(), "synchronise before capture");
     Blob blob;
     std::vector<int> job_frame;
     char *tb = ctx->ws + ctx->off_table[1];
@@ -849,6 +856,7 @@ void psweep_destroy(psweep_ctx *ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (int b = 0; b < 2; ++b) {
         if (ctx->staging[b]) (void)hipHostFree(ctx->staging[b]);
         if (ctx->staging_ev[b]) (void)hipEventDestroy(ctx->staging_ev[b]);

@@ -214,15 +214,16 @@ struct Backward {
                                 rank += (c4[t] < c4[s] || (c4[t] == c4[s] && t < s)) ? 1 : 0;
                             const bool chosen = live && c4[s] < __builtin_huge_valf() && rank < kk &&
                                                 __builtin_fabsf(zs[s]) < 1.0f;
-                            const float G = chosen ? -0.5f * dC / (float)kk : 0.0f;   // dL/dZ
+                            const float G = -0.5f * dC / (float)kk;   // dL/dZ of a chosen window
                             const float invD = isd_a[i] * rsb[s];
                             const float varb_inv = rsb[s] * rsb[s];
                             const float bbar = hbs[s] * invN;
+                            // unusable windows hold NaN/inf statistics: select, never multiply by 0
                             float *ch = chan + (((size_t)s * NCH) * TYO + wave * R + i) * kWave + lane;
-                            ch[0] = G * invD;
-                            ch[(size_t)TYO * kWave] = G * mean_a[i] * invD;
-                            ch[(size_t)2 * TYO * kWave] = G * zs[s] * varb_inv;
-                            ch[(size_t)3 * TYO * kWave] = G * zs[s] * bbar * varb_inv;
+                            ch[0] = chosen ? G * invD : 0.0f;
+                            ch[(size_t)TYO * kWave] = chosen ? G * mean_a[i] * invD : 0.0f;
+                            ch[(size_t)2 * TYO * kWave] = chosen ? G * zs[s] * varb_inv : 0.0f;
+                            ch[(size_t)3 * TYO * kWave] = chosen ? G * zs[s] * bbar * varb_inv : 0.0f;
                         }
                     }
                 }
