@@ -199,6 +199,34 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
  * autotuner.  EINVAL for other values. */
 psweep_status psweep_set_tile(psweep_ctx *ctx, int32_t level, int32_t rows_per_wave, int32_t waves);
 
+/* Depth-map filtering parameters (Sec. III-A): the best-cost threshold for
+ * pixels looking above the ground plane's horizon (alpha_upper, paper 0.05)
+ * and below it (alpha_lower, paper 0.3); the minimum ratio cost2 / cost1
+ * (the paper gives none); the continuity tolerance gamma_m (paper 0.5 m) and
+ * the minimum fraction delta (paper 0.3) of the other pixels of an odd
+ * window x window neighbourhood that must lie within gamma_m. */
+typedef struct {
+    double alpha_upper, alpha_lower, ratio_min, gamma_m, delta;
+    int32_t window;
+} psweep_filter_params;
+
+/* Filter a full-resolution map of camera set `camera_set` (in: depth, cost1,
+ * cost2 and pitch of a psweep_run output) in the paper's order: best cost,
+ * uniqueness ratio, local continuity (on the pixels that passed the first
+ * two).  Writes the kept range (NaN elsewhere) and a code per pixel: 0 kept,
+ * 1 cost, 2 ratio, 3 continuity, 255 invalid before filtering.  Asynchronous
+ * on hip_stream; EINVAL for bad parameters or pitches. */
+psweep_status psweep_filter(psweep_ctx *ctx, int32_t camera_set, const psweep_maps *in,
+                            const psweep_filter_params *params, float *out_depth, uint8_t *out_code,
+                            int64_t out_pitch, void *hip_stream);
+
+/* Plane chunks per tile for one level: each tile's planes are cut into
+ * n_chunks contiguous ranges swept by separate workgroups (more parallelism
+ * on small images) and combined exactly afterwards; 0 = automatic (about three
+ * waves per SIMD), 1 = one pass over all planes, at most 8.  Results do not
+ * depend on the choice (bitwise, winner-take-all mode). */
+psweep_status psweep_set_chunks(psweep_ctx *ctx, int32_t level, int32_t n_chunks);
+
 /* Capture one psweep_run of these frames into a HIP graph owned by the
  * context (replacing any earlier graph).  The frame and output pointers are
  * baked in.  The capture runs on a stream of the context's own after a device

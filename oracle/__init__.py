@@ -95,6 +95,8 @@ def lib():
     L.or_soft_forward.restype = None
     L.or_soft_backward.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i32, _i32, _i32, _i32, _p, _p, _p]
     L.or_soft_backward.restype = None
+    L.or_filter.argtypes = [PC, _p, _i32, _i32, _p, _p, _p, _d, _d, _d, _d, _d, _i32, _p, _p]
+    L.or_filter.restype = None
     return L
 
 
@@ -377,3 +379,24 @@ def soft_backward(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, 
                            g.ctypes.data, gptrs, gp.ctypes.data)
     del keep
     return gs, gp.reshape(-1, 6)
+
+
+# ----------------------------------------------------------------------------
+# depth-map filtering (Sec. III-A)
+# ----------------------------------------------------------------------------
+def depth_filter(cam, ground_n, depth, cost1, cost2, alpha_upper=0.05, alpha_lower=0.3, ratio_min=1.05,
+                 gamma=0.5, delta=0.3, window=5):
+    """Best-cost, uniqueness-ratio and local-continuity filters, in that
+    order.  Returns (filtered range with NaN for rejected pixels, code: 0
+    kept, 1 cost, 2 uniqueness, 3 continuity, 255 invalid)."""
+    d = np.ascontiguousarray(np.asarray(depth, np.float64))
+    a = np.ascontiguousarray(np.asarray(cost1, np.float64))
+    b = np.ascontiguousarray(np.asarray(cost2, np.float64))
+    h, w = d.shape
+    gn = np.ascontiguousarray(np.asarray(ground_n, np.float64))
+    out = np.empty_like(d)
+    code = np.empty((h, w), np.uint8)
+    lib().or_filter(ctypes.byref(camera(cam)), gn.ctypes.data, w, h, d.ctypes.data, a.ctypes.data, b.ctypes.data,
+                    float(alpha_upper), float(alpha_lower), float(ratio_min), float(gamma), float(delta),
+                    int(window), out.ctypes.data, code.ctypes.data)
+    return out, code

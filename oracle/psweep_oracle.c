@@ -605,3 +605,63 @@ void or_soft_backward(const or_params *p, const or_camera *rc, const or_image *r
         }
     free(C); free(Cs); free(bb);
 }
+
+/* ------------------------------------------------------------------------ */
+/* depth-map filtering (Sec. III-A, depth map filtering)                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Three tests, applied in the order the paper shows them (Fig. 3):
+ *   1. best cost: c1 > alpha is an outlier, with alpha_upper for pixels whose
+ *      ray points above the ground plane's horizon (n_g . r <= 0, the upper
+ *      part of the view) and alpha_lower below it;
+ *   2. uniqueness: the ratio c2 / c1 of the second best to the best cost
+ *      must reach ratio_min (a larger ratio is a more unique depth);
+ *   3. local continuity: among the other pixels of the win x win window that
+ *      survived tests 1-2, count those whose range differs from the centre's
+ *      by less than gamma; the pixel is rejected when that count over
+ *      (win^2 - 1) is below delta_frac.
+ * Inputs are the sweep's full-resolution maps; out_depth is the range with
+ * rejected pixels set to NaN, code is 0 kept, 1 cost, 2 uniqueness,
+ * 3 continuity, 255 invalid before filtering.
+ */
+void or_filter(const or_camera *cam, const double ground_n[3], int32_t w, int32_t h,
+               const double *depth, const double *c1, const double *c2,
+               double alpha_upper, double alpha_lower, double ratio_min, double gamma, double delta_frac,
+               int32_t win, double *out_depth, uint8_t *code)
+{
+    const int hw = win / 2;
+    double *d1 = (double *)malloc(sizeof(double) * (size_t)w * h);
+    for (int j = 0; j < h; ++j)
+        for (int i = 0; i < w; ++i) {
+            int64_t e = (int64_t)j * w + i;
+            d1[e] = NAN;
+            if (isnan(depth[e])) { code[e] = 255; continue; }
+            double r[3];
+            or_unproject(cam, i, j, r);
+            double up = ground_n[0] * r[0] + ground_n[1] * r[1] + ground_n[2] * r[2];
+            double alpha = up <= 0.0 ? alpha_upper : alpha_lower;
+            if (c1[e] > alpha) { code[e] = 1; continue; }
+            if (!(c2[e] >= ratio_min * c1[e])) { code[e] = 2; continue; }
+            code[e] = 0;
+            d1[e] = depth[e];
+        }
+    for (int j = 0; j < h; ++j)
+        for (int i = 0; i < w; ++i) {
+            int64_t e = (int64_t)j * w + i;
+            out_depth[e] = NAN;
+            if (code[e] != 0) continue;
+            int cons = 0;
+            for (int dj = -hw; dj <= hw; ++dj)
+                for (int di = -hw; di <= hw; ++di) {
+                    if (di == 0 && dj == 0) continue;
+                    int ii = i + di, jj = j + dj;
+                    if (ii < 0 || jj < 0 || ii >= w || jj >= h) continue;
+                    double q = d1[(int64_t)jj * w + ii];
+                    if (!isnan(q) && fabs(q - d1[e]) < gamma) ++cons;
+                }
+            if ((double)cons < delta_frac * (win * win - 1)) { code[e] = 3; continue; }
+            out_depth[e] = d1[e];
+        }
+    free(d1);
+}

@@ -21,6 +21,8 @@ extern "C" const void *psw_prep_kernel();
 extern "C" const void *psw_border_kernel();
 extern "C" const void *psw_reset_kernel();
 extern "C" const void *psw_merge_kernel();
+extern "C" const void *psw_chunk_merge_kernel();
+extern "C" const void *psw_filter_kernel();
 extern "C" const void *psw_backward_kernel(int win, int n_src);
 extern "C" size_t psw_backward_lds(int win, int n_src);
 extern "C" const void *psw_zero_kernel();
@@ -114,6 +116,9 @@ struct psweep_ctx {
     std::vector<char> last_table;
     uint64_t cam_version = 1, setup_version = 0;
     int tile_rows[PSWEEP_MAX_LEVELS] = {8, 8}, tile_waves[PSWEEP_MAX_LEVELS] = {4, 4};
+    int chunks[PSWEEP_MAX_LEVELS] = {0, 0};   // plane chunks per tile; 0 = automatic
+    int n_cu = 256;
+    size_t s_part[PSWEEP_MAX_LEVELS] = {0, 0};
     // timing of sweep launches
     bool timing = false;
     std::vector<hipEvent_t> ev0, ev1;
@@ -261,6 +266,7 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
         ctx->s_maps[l] = so;  so += align_up(rpx * 4) * 4;
         ctx->s_htab[l] = so;  so += align_up((size_t)ctx->P[l] * S * 9 * 4);
         ctx->s_theta[l] = so; so += align_up((size_t)ctx->P[l] * 4);
+        ctx->s_part[l] = so;  so += align_up(rpx * 4 * kPartWords * kMaxChunks);
     }
     ctx->slot_bytes = align_up(so);
     ctx->ws_need = ctx->off_slots + ctx->slot_bytes * cfg->max_frames;
@@ -270,6 +276,12 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
             psweep_destroy(ctx);
             return fail(nullptr, PSWEEP_EHIP, "pinned staging allocation failed");
         }
+    }
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ctx->n_cu = prop.multiProcessorCount;
     }
     load_tables();
     // kernels with more than 64 KB of dynamic LDS need the limit raised
@@ -349,6 +361,14 @@ psweep_status psweep_set_tile(psweep_ctx *ctx, int32_t level, int32_t rows_per_w
         return fail(ctx, PSWEEP_EINVAL, "rows_per_wave must be 8 or 16 and waves 2 or 4");
     ctx->tile_rows[level] = rows_per_wave;
     ctx->tile_waves[level] = waves;
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_set_chunks(psweep_ctx *ctx, int32_t level, int32_t n_chunks) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (level < 0 || level >= ctx->cfg.n_levels) return fail(ctx, PSWEEP_EINVAL, "level out of range");
+    if (n_chunks < 0 || n_chunks > kMaxChunks) return fail(ctx, PSWEEP_EINVAL, "n_chunks out of [0, 8]");
+    ctx->chunks[level] = n_chunks;
     return PSWEEP_OK;
 }
 
@@ -487,9 +507,31 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             const int TYO = rows * waves;
             J.tiles_x = rc.w > 2 * hw ? (rc.w - 2 * hw + TXO - 1) / TXO : 0;
             J.tiles_y = rc.h > 2 * hw ? (rc.h - 2 * hw + TYO - 1) / TYO : 0;
-            J.first_item = first_item;
-            first_item += J.tiles_x * J.tiles_y;
             J.rows = rows; J.waves = waves;
+            // plane chunks: enough workgroups for about three waves per SIMD
+            {
+                const int ntile = J.tiles_x * J.tiles_y;
+                int nch = ctx->chunks[l];
+                if (nch == 0) {
+                    const long long target = 3LL * ctx->n_cu * 4;
+                    const long long have = (long long)ntile * waves * (cfg.launch == PSWEEP_LAUNCH_PERSISTENT ? nf : 1);
+                    nch = have > 0 ? (int)((target + have - 1) / have) : 1;
+                    nch = std::max(1, std::min(nch, kMaxChunks));
+                }
+                if (cfg.mode == PSWEEP_MODE_SOFT && nch > 1) nch = std::min(nch, std::max(1, L.n_fronto / 2));
+                J.nch_f = 0; J.nch_g = 0;
+                if (nch > 1) {
+                    const int cs = (P + nch - 1) / nch;
+                    J.nch_f = L.n_fronto > 0 ? (L.n_fronto + cs - 1) / cs : 0;
+                    J.nch_g = L.n_ground > 0 ? (L.n_ground + cs - 1) / cs : 0;
+                    while (J.nch_f + J.nch_g > kMaxChunks) { if (J.nch_f >= J.nch_g) --J.nch_f; else --J.nch_g; }
+                    if (J.nch_f + J.nch_g <= 1) { J.nch_f = 0; J.nch_g = 0; }
+                }
+                J.part = (float *)(slot + ctx->s_part[l]);
+                const int items = ntile * std::max(1, J.nch_f + J.nch_g);
+                J.first_item = first_item;
+                first_item += items;
+            }
             for (int s = 0; s < C.n_src; ++s) {
                 const LevelCam sc = level_cam(C.src[s], ds, 0, 0, 0, 0);
                 SrcDev &D = J.src[s];
@@ -630,7 +672,7 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
     if (cfg.launch == PSWEEP_LAUNCH_GRID) {
         for (int j = 0; j < nj; ++j) {
             const JobDev &J = (*host_jobs)[j];
-            const int nt = J.tiles_x * J.tiles_y;
+            const int nt = J.tiles_x * J.tiles_y * std::max(1, J.nch_f + J.nch_g);
             if (nt == 0) continue;
             const KernelEntry *e = find_kernel(J.window, J.rows, J.waves, J.n_src, store, soft, 0);
             if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no kernel for this window/tile/sources/storage");
@@ -645,7 +687,7 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
         int n_items = 0, n_src = (*host_jobs)[0].n_src;
         for (int j = 0; j < nj; ++j) {
             const JobDev &J = (*host_jobs)[j];
-            n_items += J.tiles_x * J.tiles_y;
+            n_items += J.tiles_x * J.tiles_y * std::max(1, J.nch_f + J.nch_g);
             if (J.n_src != n_src) return fail(ctx, PSWEEP_EUNSUPPORTED, "persistent launch needs one source count");
             if (J.rows != ctx->tile_rows[0] || J.waves != ctx->tile_waves[0])
                 return fail(ctx, PSWEEP_EUNSUPPORTED, "persistent launch needs one tile shape");
@@ -674,6 +716,12 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
             PSW_HIP(hipLaunchKernel(e->fn, dim3(grid), dim3(kWave * ctx->tile_waves[0]), a, e->lds, stream), "sweep");
             if (timed) { PSW_HIP(hipEventRecord(ctx->ev1[0], stream), "event record"); ctx->n_timed = 1; }
         }
+    }
+    bool any_chunks = false;
+    for (int j = 0; j < nj; ++j) any_chunks |= (*host_jobs)[j].nch_f + (*host_jobs)[j].nch_g > 1;
+    if (any_chunks) {
+        void *a[] = {&dj};
+        PSW_HIP(hipLaunchKernel(psw_chunk_merge_kernel(), dim3(512, nj), dim3(256), a, 0, stream), "chunk merge");
     }
     if (blob.nm > 0) {
         void *a[] = {&dm};
@@ -848,6 +896,41 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     void *a[] = {(void *)&job, (void *)&d_grad_invdepth, (void *)&rho, (void *)&lse, &sp,
                  &g0, &g1, &g2, &g3, &d_grad_pose};
     PSW_HIP(hipLaunchKernel(bk, dim3(tx, ty), dim3(256), a, lds, stream), "backward");
+    return PSWEEP_OK;
+}
+
+psweep_status psweep_filter(psweep_ctx *ctx, int32_t camera_set, const psweep_maps *in,
+                            const psweep_filter_params *prm, float *out_depth, uint8_t *out_code, int64_t out_pitch,
+                            void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (camera_set < 0 || camera_set >= (int)ctx->sets.size() || !ctx->sets[camera_set].defined)
+        return fail(ctx, PSWEEP_ESTATE, "undefined camera set");
+    if (!in || !prm || !in->depth || !in->cost1 || !in->cost2 || !out_depth || !out_code)
+        return fail(ctx, PSWEEP_EINVAL, "NULL map");
+    if (prm->window < 3 || prm->window > 15 || (prm->window & 1) == 0)
+        return fail(ctx, PSWEEP_EINVAL, "filter window must be odd in [3, 15]");
+    if (!(prm->gamma_m > 0.0) || !(prm->delta >= 0.0 && prm->delta <= 1.0) || !(prm->ratio_min >= 1.0))
+        return fail(ctx, PSWEEP_EINVAL, "need gamma > 0, 0 <= delta <= 1, ratio_min >= 1");
+    const psweep_camera &c = ctx->sets[camera_set].ref;
+    if ((in->pitch != 0 && in->pitch < c.width) || (out_pitch != 0 && out_pitch < c.width))
+        return fail(ctx, PSWEEP_EINVAL, "pitch below width");
+    if (!ctx->ws) return fail(ctx, PSWEEP_ESTATE, "psweep_set_workspace has not been called");
+    FilterDev F;
+    std::memset(&F, 0, sizeof F);
+    F.w = c.width; F.h = c.height; F.win = prm->window;
+    F.fx = (float)c.fx; F.fy = (float)c.fy; F.cx = (float)c.cx; F.cy = (float)c.cy; F.xi = (float)c.xi;
+    for (int a = 0; a < 3; ++a) F.gn[a] = (float)ctx->cfg.ground_n[a];
+    F.alpha_upper = (float)prm->alpha_upper; F.alpha_lower = (float)prm->alpha_lower;
+    F.ratio_min = (float)prm->ratio_min; F.gamma = (float)prm->gamma_m;
+    F.min_count = (float)(prm->delta * (prm->window * prm->window - 1));
+    F.depth = in->depth; F.cost1 = in->cost1; F.cost2 = in->cost2;
+    F.in_pitch = in->pitch ? in->pitch : c.width;
+    F.out_depth = out_depth; F.code = out_code;
+    F.out_pitch = out_pitch ? out_pitch : c.width;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    void *a[] = {&F};
+    PSW_HIP(hipLaunchKernel(psw_filter_kernel(), dim3((c.width + 15) / 16, (c.height + 15) / 16), dim3(16, 16), a, 0,
+                            stream), "filter");
     return PSWEEP_OK;
 }
 

@@ -176,9 +176,130 @@ __global__ void merge_kernel(const MergeDev *__restrict__ ms) {
     }
 }
 
+// Combine the partial states of a tile's plane chunks, in plane order: the
+// winner is the lowest-index minimum, the second best the minimum over every
+// other plane, and a winner at a chunk edge takes its neighbour's cost from
+// the adjacent chunk of the same family.  Soft mode merges running
+// log-sum-exp states.
+__global__ void chunk_merge_kernel(const JobDev *__restrict__ jobs) {
+    const JobDev &J = jobs[blockIdx.y];
+    const int nch = J.nch_f + J.nch_g;
+    if (nch <= 1) return;
+    const int hw = J.window / 2;
+    const int iw = J.w - 2 * hw, ih = J.h - 2 * hw;
+    if (iw <= 0 || ih <= 0) return;
+    const size_t plane = (size_t)J.h * J.w;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < iw * ih; e += gridDim.x * blockDim.x) {
+        const int col = hw + e % iw, row = hw + e / iw;
+        const float *p = J.part + (size_t)row * J.w + col;
+        if (J.mode == 1) {
+            float mx = -PSW_INF;
+            for (int c = 0; c < nch; ++c) mx = fmaxf(mx, p[(size_t)c * kPartWords * plane]);
+            float se = 0.0f, sr = 0.0f;
+            if (mx > -PSW_INF) {
+                for (int c = 0; c < nch; ++c) {
+                    const float m = p[(size_t)c * kPartWords * plane];
+                    if (m > -PSW_INF) {
+                        const float f = __expf(m - mx);
+                        se = fmaf(p[((size_t)c * kPartWords + 1) * plane], f, se);
+                        sr = fmaf(p[((size_t)c * kPartWords + 2) * plane], f, sr);
+                    }
+                }
+            }
+            finish_soft(J, row, col, mx, se, sr);
+            continue;
+        }
+        float best = PSW_INF;
+        int win = -1;
+        for (int c = 0; c < nch; ++c) {
+            const float v = p[(size_t)c * kPartWords * plane];
+            if (v < best) { best = v; win = c; }
+        }
+        const float x = ((float)col - J.cx) * J.inv_fx;
+        if (win < 0) {
+            finish_pixel(J, x, row, col, -1, PSW_INF, PSW_INF, PSW_INF, PSW_INF);
+            continue;
+        }
+        const float *q = p + (size_t)win * kPartWords * plane;
+        const int k = __float_as_int(q[plane]);
+        float c2 = q[2 * plane], cm = q[3 * plane], cp = q[4 * plane];
+        for (int c = 0; c < nch; ++c)
+            if (c != win) c2 = fminf(c2, p[(size_t)c * kPartWords * plane]);
+        int a, b;
+        chunk_range(J.n_fronto, J.n_ground, J.nch_f, J.nch_g, win, &a, &b);
+        const bool fam = win < J.nch_f;
+        if (k == a && win > 0 && ((win - 1 < J.nch_f) == fam))
+            cm = p[((size_t)(win - 1) * kPartWords + 6) * plane];
+        if (k == b - 1 && win + 1 < nch && ((win + 1 < J.nch_f) == fam))
+            cp = p[((size_t)(win + 1) * kPartWords + 5) * plane];
+        finish_pixel(J, x, row, col, k, best, c2, cm, cp);
+    }
+}
+
+// Depth-map filtering (Sec. III-A): best-cost threshold per image part
+// (above / below the ground plane's horizon), second-to-best cost ratio,
+// then local continuity over a window of the pixels that passed.  16x16
+// output pixels per workgroup; the first two tests are evaluated once per
+// pixel of the tile and its halo into LDS, then every thread counts its
+// consistent neighbours there.
+constexpr int kFT = 16;
+constexpr int kFMaxHalo = 7;
+__global__ __launch_bounds__(256) void filter_kernel(const FilterDev F) {
+    __shared__ float d1[(kFT + 2 * kFMaxHalo) * (kFT + 2 * kFMaxHalo)];
+    __shared__ uint8_t c1code[(kFT + 2 * kFMaxHalo) * (kFT + 2 * kFMaxHalo)];
+    const int hw = F.win / 2;
+    const int tw = kFT + 2 * hw;
+    const int x0 = blockIdx.x * kFT - hw, y0 = blockIdx.y * kFT - hw;
+    const int tid = threadIdx.y * kFT + threadIdx.x;
+    for (int e = tid; e < tw * tw; e += kFT * kFT) {
+        const int x = x0 + e % tw, y = y0 + e / tw;
+        float v = __builtin_nanf("");
+        uint8_t code = 255;
+        if (x >= 0 && y >= 0 && x < F.w && y < F.h) {
+            const int64_t o = (int64_t)y * F.in_pitch + x;
+            const float d = F.depth[o];
+            if (!__builtin_isnan(d)) {
+                const float xn = ((float)x - F.cx) / F.fx, yn = ((float)y - F.cy) / F.fy;
+                const float t = ray_tau(xn, yn, F.xi, nullptr);
+                const float up = fmaf(F.gn[0], xn, fmaf(F.gn[1], yn, F.gn[2] * t));
+                const float alpha = up <= 0.0f ? F.alpha_upper : F.alpha_lower;
+                const float a = F.cost1[o], b = F.cost2[o];
+                if (a > alpha) code = 1;
+                else if (!(b >= F.ratio_min * a)) code = 2;
+                else { code = 0; v = d; }
+            }
+        }
+        d1[e] = v;
+        c1code[e] = code;
+    }
+    __syncthreads();
+    const int x = blockIdx.x * kFT + threadIdx.x, y = blockIdx.y * kFT + threadIdx.y;
+    if (x >= F.w || y >= F.h) return;
+    const int le = (threadIdx.y + hw) * tw + threadIdx.x + hw;
+    uint8_t code = c1code[le];
+    float out = __builtin_nanf("");
+    if (code == 0) {
+        const float d = d1[le];
+        int cons = 0;
+        for (int dj = -hw; dj <= hw; ++dj)
+            for (int di = -hw; di <= hw; ++di) {
+                if (di == 0 && dj == 0) continue;
+                const float q = d1[le + dj * tw + di];
+                cons += __builtin_fabsf(q - d) < F.gamma ? 1 : 0;   // NaN compares false
+            }
+        if ((float)cons < F.min_count) code = 3;
+        else out = d;
+    }
+    const int64_t o = (int64_t)y * F.out_pitch + x;
+    F.out_depth[o] = out;
+    F.code[o] = code;
+}
+
 }  // namespace psw
 
 extern "C" {
+const void *psw_filter_kernel() { return (const void *)&psw::filter_kernel; }
+const void *psw_chunk_merge_kernel() { return (const void *)&psw::chunk_merge_kernel; }
 const void *psw_setup_kernel() { return (const void *)&psw::setup_kernel; }
 const void *psw_prep_kernel() { return (const void *)&psw::prep_kernel; }
 const void *psw_border_kernel() { return (const void *)&psw::border_kernel; }

@@ -47,8 +47,30 @@ struct JobDev {
     int32_t tiles_x, tiles_y, first_item, pad0;
     // tile shape used for this job by the grid launch (rows per wave, waves)
     int32_t rows, waves, pad1, pad2;
+    // plane chunks: the fronto planes are cut into nch_f contiguous chunks and
+    // the ground planes into nch_g; with more than one chunk every chunk of a
+    // tile writes a partial state (kPartWords words per pixel) that
+    // chunk_merge_kernel combines
+    int32_t nch_f, nch_g, pad3, pad4;
+    float *part;           // [chunk][word][h][w], pitch w
     SrcDev src[kMaxSrc];
 };
+
+constexpr int kPartWords = 7;   // c1, kb, c2, cm, cp, first, last (soft: max, sum, sum*theta)
+constexpr int kMaxChunks = 8;
+
+// plane range [kb, ke) of chunk c of a job (chunks never straddle families)
+__host__ __device__ inline void chunk_range(int n_fronto, int n_ground, int nch_f, int nch_g, int c, int *kb,
+                                            int *ke) {
+    if (c < nch_f) {
+        *kb = (int)((long long)c * n_fronto / nch_f);
+        *ke = (int)((long long)(c + 1) * n_fronto / nch_f);
+    } else {
+        const int g = c - nch_f;
+        *kb = n_fronto + (int)((long long)g * n_ground / nch_g);
+        *ke = n_fronto + (int)((long long)(g + 1) * n_ground / nch_g);
+    }
+}
 
 // FP64 description of one (frame, level) for the setup kernel.
 struct SetupDev {
@@ -119,6 +141,19 @@ struct BorderDev {
 }  // namespace psw
 
 namespace psw {
+
+// Depth-map filtering of one full-resolution map.
+struct FilterDev {
+    int32_t w, h, win, pad;
+    float fx, fy, cx, cy, xi;
+    float gn[3];
+    float alpha_upper, alpha_lower, ratio_min, gamma, min_count;
+    const float *depth, *cost1, *cost2;
+    int64_t in_pitch;
+    float *out_depth;
+    uint8_t *code;
+    int64_t out_pitch;
+};
 
 // One compiled variant of the sweep kernel.
 struct KernelEntry {

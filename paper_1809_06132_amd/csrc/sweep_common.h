@@ -162,6 +162,48 @@ __device__ __forceinline__ float aggregate(const float c[4], int K) {
     return (m0 < PSW_INF) ? acc * __builtin_amdgcn_rcpf(cnt) : PSW_INF;
 }
 
+// Winner-take-all result of one pixel: parabolic subpixel step through the
+// winner and its two same-family neighbours (missing neighbour = +inf), the
+// refined plane parameter, the range along the Eq. (1) ray and z.
+__device__ __forceinline__ void finish_pixel(const JobDev &J, float x, int orow, int col, int k, float c1, float c2,
+                                             float cm, float cp) {
+    const int64_t o = (int64_t)orow * J.out_pitch + col;
+    float dl = 0.0f, depth = __builtin_nanf(""), zz = __builtin_nanf("");
+    if (k >= 0) {
+        if (cm < PSW_INF && cp < PSW_INF) {
+            const float den = cm - 2.0f * c1 + cp;
+            if (den > 0.0f) dl = __builtin_amdgcn_fmed3f((cm - cp) / (2.0f * den), -0.5f, 0.5f);
+        }
+        const bool fr = k < J.n_fronto;
+        const float th = cptr(J.theta)[k] + dl * (fr ? J.step_f : J.step_g);
+        const float y = ((float)orow - J.cy) * J.inv_fy;
+        float eta;
+        const float t = ray_tau(x, y, J.xi, &eta);
+        const float rz = eta * t;
+        if (fr) {
+            depth = 1.0f / (th * rz);
+        } else {
+            const float nr = eta * fmaf(J.gn[0], x, fmaf(J.gn[1], y, J.gn[2] * t));
+            depth = (J.gd - th) / nr;
+        }
+        zz = depth * rz;
+    }
+    if (J.index) gptr(J.index)[o] = k;
+    if (J.delta) gptr(J.delta)[o] = dl;
+    if (J.cost1) gptr(J.cost1)[o] = k >= 0 ? c1 : PSW_INF;
+    if (J.cost2) gptr(J.cost2)[o] = k >= 0 ? c2 : PSW_INF;
+    if (J.depth) gptr(J.depth)[o] = depth;
+    if (J.z) gptr(J.z)[o] = zz;
+    if (J.level_id) gptr(J.level_id)[o] = k >= 0 ? 0 : 255;
+}
+
+__device__ __forceinline__ void finish_soft(const JobDev &J, int orow, int col, float mx, float se, float sr) {
+    const bool ok = mx > -PSW_INF;
+    const int64_t so = (int64_t)orow * J.soft_pitch + col;
+    gptr(J.soft_rho)[so] = ok ? sr / se : __builtin_nanf("");
+    gptr(J.soft_lse)[so] = ok ? mx + __logf(se) : -PSW_INF;
+}
+
 // ---------------------------------------------------------------------------
 // the sweep of one tile
 // ---------------------------------------------------------------------------
@@ -178,7 +220,7 @@ struct Tile {
 
     static constexpr size_t lds_bytes() { return (size_t)S * T * kWave * sizeof(ST); }
 
-    __device__ static void run(const JobDev *__restrict__ Jp, int tile_x, int tile_y, char *smem) {
+    __device__ static void run(const JobDev *__restrict__ Jp, int tile_x, int tile_y, int chunk, char *smem) {
         const JobDev &J = *Jp;
         ST *tile = reinterpret_cast<ST *>(smem);
         const int lane = threadIdx.x & (kWave - 1);
@@ -259,10 +301,24 @@ struct Tile {
         const float invN = 1.0f / (float)(WIN * WIN);
         const float vfn = J.var_floor_n;
 
+        // planes this workgroup sweeps: every plane, or one chunk of them
+        const int nch = J.nch_f + J.nch_g;
+        int k_lo[2] = {0, J.n_fronto}, k_hi[2] = {J.n_fronto, J.n_fronto + J.n_ground};
+        if (nch > 1) {
+            int a, b;
+            chunk_range(J.n_fronto, J.n_ground, J.nch_f, J.nch_g, chunk, &a, &b);
+            const int f = a >= J.n_fronto ? 1 : 0;
+            k_lo[f] = a; k_hi[f] = b;
+            k_lo[1 - f] = 0; k_hi[1 - f] = 0;
+        }
+        float cfirst[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) cfirst[i] = PSW_INF;
+
         for (int fam = 0; fam < 2; ++fam) {
-            const int np = fam ? J.n_ground : J.n_fronto;
-            if (np == 0) continue;
-            const int k0 = fam ? J.n_fronto : 0;
+            const int np = k_hi[fam] - k_lo[fam];
+            if (np <= 0) continue;
+            const int k0 = k_lo[fam];
             // family ray parameter: tau where the family's planes are hit in
             // front of the camera, NaN elsewhere (NaN fails every later test)
             float tf[NWR];
@@ -369,6 +425,7 @@ struct Tile {
                         const float C0 = aggregate<S>(cs4, K);
                         float C = C0;
                         C = ((ref_ok >> i) & 1u) ? C : PSW_INF;
+                        if (kk == 0) cfirst[i] = C;
                         if (!SOFT) {
                             const bool nb = C < c1[i];
                             const bool fill = (kb[i] == k - 1) && (kk > 0);
@@ -398,42 +455,24 @@ struct Tile {
         for (int i = 0; i < R; ++i) {
             if (!((pos_ok >> i) & 1u)) continue;
             const int orow = or0 + i;
-            if (SOFT) {
-                const bool ok = c1[i] > -PSW_INF;
-                const int64_t so = (int64_t)orow * J.soft_pitch + sc;
-                gptr(J.soft_rho)[so] = ok ? cm[i] / c2[i] : __builtin_nanf("");
-                gptr(J.soft_lse)[so] = ok ? c1[i] + __logf(c2[i]) : -PSW_INF;
+            if (nch > 1) {
+                // partial state of this chunk, combined by chunk_merge_kernel
+                const size_t plane = (size_t)H * W;
+                float *pp = J.part + (size_t)chunk * kPartWords * plane + (size_t)orow * W + sc;
+                PSW_GLOBAL float *g = gptr(pp);
+                g[0] = c1[i];
+                g[plane] = SOFT ? c2[i] : __int_as_float(kb[i]);
+                g[2 * plane] = SOFT ? cm[i] : c2[i];
+                if (!SOFT) {
+                    g[3 * plane] = cm[i];
+                    g[4 * plane] = cp[i];
+                    g[5 * plane] = cfirst[i];
+                    g[6 * plane] = cprev[i];
+                }
                 continue;
             }
-            const int64_t o = (int64_t)orow * J.out_pitch + sc;
-            const int k = kb[i];
-            float dl = 0.0f, depth = __builtin_nanf(""), zz = __builtin_nanf("");
-            if (k >= 0) {
-                if (cm[i] < PSW_INF && cp[i] < PSW_INF) {
-                    const float den = cm[i] - 2.0f * c1[i] + cp[i];
-                    if (den > 0.0f) dl = __builtin_amdgcn_fmed3f((cm[i] - cp[i]) / (2.0f * den), -0.5f, 0.5f);
-                }
-                const bool fr = k < J.n_fronto;
-                const float th = cptr(J.theta)[k] + dl * (fr ? J.step_f : J.step_g);
-                const float y = ((float)orow - J.cy) * J.inv_fy;
-                float eta;
-                const float t = ray_tau(x, y, xi, &eta);
-                const float rz = eta * t;
-                if (fr) {
-                    depth = 1.0f / (th * rz);
-                } else {
-                    const float nr = eta * fmaf(J.gn[0], x, fmaf(J.gn[1], y, J.gn[2] * t));
-                    depth = (J.gd - th) / nr;
-                }
-                zz = depth * rz;
-            }
-            if (J.index) gptr(J.index)[o] = k;
-            if (J.delta) gptr(J.delta)[o] = dl;
-            if (J.cost1) gptr(J.cost1)[o] = c1[i];
-            if (J.cost2) gptr(J.cost2)[o] = k >= 0 ? c2[i] : PSW_INF;
-            if (J.depth) gptr(J.depth)[o] = depth;
-            if (J.z) gptr(J.z)[o] = zz;
-            if (J.level_id) gptr(J.level_id)[o] = k >= 0 ? 0 : 255;
+            if (SOFT) finish_soft(J, orow, sc, c1[i], c2[i], cm[i]);
+            else finish_pixel(J, x, orow, sc, kb[i], c1[i], c2[i], cm[i], cp[i]);
         }
     }
 };
@@ -448,12 +487,15 @@ struct Tile {
 template <int WIN, int R, int NW, int S, int STORE, bool SOFT>
 __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__restrict__ job) {
     extern __shared__ char smem[];
-    const int nt = job->tiles_x * job->tiles_y;
+    const int ntile = job->tiles_x * job->tiles_y;
+    const int nch = job->nch_f + job->nch_g;
+    const int nt = ntile * (nch > 1 ? nch : 1);
     const int per = (nt + 7) / 8;
     const int b = blockIdx.x;
     const int t = (b & 7) * per + (b >> 3);
     if (t >= nt) return;
-    Tile<WIN, R, NW, S, STORE, SOFT>::run(job, t % job->tiles_x, t / job->tiles_x, smem);
+    const int tile = t % ntile, chunk = t / ntile;
+    Tile<WIN, R, NW, S, STORE, SOFT>::run(job, tile % job->tiles_x, tile / job->tiles_x, chunk, smem);
 }
 
 // One persistent launch for every (frame, level, tile) of a run: workgroups
@@ -474,9 +516,11 @@ __global__ __launch_bounds__(kWave *NW) void sweep_persistent_kernel(const JobDe
         while (j + 1 < n_jobs && jobs[j + 1].first_item <= item) ++j;
         const JobDev *J = jobs + j;
         const int t = item - J->first_item;
-        const int tx = t % J->tiles_x, ty = t / J->tiles_x;
-        if (J->window == 7) Tile<7, R, NW, S, STORE, false>::run(J, tx, ty, smem);
-        else Tile<9, R, NW, S, STORE, false>::run(J, tx, ty, smem);
+        const int ntile = J->tiles_x * J->tiles_y;
+        const int tile = t % ntile, chunk = t / ntile;
+        const int tx = tile % J->tiles_x, ty = tile / J->tiles_x;
+        if (J->window == 7) Tile<7, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem);
+        else Tile<9, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem);
     }
 }
 

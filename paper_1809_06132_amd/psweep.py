@@ -25,7 +25,7 @@ _d, _i32, _i64, _p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_v
 EXPORTS = ["psweep_create", "psweep_workspace_size", "psweep_set_workspace", "psweep_set_cameras",
            "psweep_set_crop", "psweep_run", "psweep_soft_depth_backward", "psweep_set_tile",
            "psweep_graph_capture", "psweep_graph_launch", "psweep_set_timing", "psweep_sweep_kernel_ms",
-           "psweep_sweep_kernel_times",
+           "psweep_sweep_kernel_times", "psweep_set_chunks", "psweep_filter",
            "psweep_plane_pixels", "psweep_destroy", "psweep_last_error", "psweep_version"]
 
 
@@ -66,6 +66,11 @@ class psweep_maps(ctypes.Structure):
                 ("level", _p), ("pitch", _i64)]
 
 
+class psweep_filter_params(ctypes.Structure):
+    _fields_ = [("alpha_upper", _d), ("alpha_lower", _d), ("ratio_min", _d), ("gamma_m", _d), ("delta", _d),
+                ("window", _i32)]
+
+
 class psweep_output(ctypes.Structure):
     _fields_ = [("merged", psweep_maps), ("level", psweep_maps * MAX_LEVELS), ("soft_invdepth", _p),
                 ("soft_lse", _p), ("soft_pitch", _i64)]
@@ -87,6 +92,8 @@ def lib() -> ctypes.CDLL:
     L.psweep_run.argtypes = [_p, P(psweep_frame), _i32, P(psweep_output), _p]
     L.psweep_soft_depth_backward.argtypes = [_p, _p, P(_p), _p, _p]
     L.psweep_set_tile.argtypes = [_p, _i32, _i32, _i32]
+    L.psweep_set_chunks.argtypes = [_p, _i32, _i32]
+    L.psweep_filter.argtypes = [_p, _i32, P(psweep_maps), P(psweep_filter_params), _p, _p, _i64, _p]
     L.psweep_graph_capture.argtypes = [_p, P(psweep_frame), _i32, P(psweep_output), _p]
     L.psweep_graph_launch.argtypes = [_p, _p]
     L.psweep_set_timing.argtypes = [_p, _i32]
@@ -159,6 +166,16 @@ def psweep_soft_depth_backward(ctx, grad_invdepth: int, grad_src_ptrs, grad_pose
 
 def psweep_set_tile(ctx, level: int, rows_per_wave: int, waves: int):
     _check(lib().psweep_set_tile(ctx, level, rows_per_wave, waves), ctx)
+
+
+def psweep_set_chunks(ctx, level: int, n_chunks: int):
+    _check(lib().psweep_set_chunks(ctx, level, n_chunks), ctx)
+
+
+def psweep_filter(ctx, camera_set: int, maps: psweep_maps, params: psweep_filter_params, out_depth: int,
+                  out_code: int, out_pitch: int = 0, stream: int = 0):
+    _check(lib().psweep_filter(ctx, camera_set, ctypes.byref(maps), ctypes.byref(params), out_depth, out_code,
+                               out_pitch, stream), ctx)
 
 
 def psweep_graph_capture(ctx, frames, outputs, stream: int = 0):

@@ -101,6 +101,9 @@ class PlaneSweep:
     def set_tile(self, level, rows_per_wave, waves):
         P.psweep_set_tile(self.ctx, level, rows_per_wave, waves)
 
+    def set_chunks(self, level, n_chunks):
+        P.psweep_set_chunks(self.ctx, level, n_chunks)
+
     def set_timing(self, on=True):
         P.psweep_set_timing(self.ctx, on)
 
@@ -189,6 +192,19 @@ class PlaneSweep:
 
     def launch_graph(self, stream=None):
         P.psweep_graph_launch(self.ctx, _stream_handle(stream))
+
+    def filter(self, merged: dict, camera_set=0, alpha_upper=0.05, alpha_lower=0.3, ratio_min=1.05, gamma=0.5,
+               delta=0.3, window=5, stream=None):
+        """Depth-map filtering of a merged output (Sec. III-A); returns the
+        filtered range (NaN = rejected) and the per-pixel code."""
+        ref, _ = self.cams[camera_set]
+        d = torch.empty((ref.height, ref.width), dtype=torch.float32, device=self.device)
+        c = torch.empty((ref.height, ref.width), dtype=torch.uint8, device=self.device)
+        prm = P.psweep_filter_params(float(alpha_upper), float(alpha_lower), float(ratio_min), float(gamma),
+                                     float(delta), int(window))
+        P.psweep_filter(self.ctx, camera_set, self._maps(merged), prm, d.data_ptr(), c.data_ptr(), 0,
+                        _stream_handle(stream))
+        return d, c
 
     def plane_pixels(self, frames) -> int:
         return P.psweep_plane_pixels(self.ctx, [self._frame(f) for f in frames])

@@ -1,0 +1,39 @@
+"""GPU depth-map filtering against the oracle's filter, on the same input
+maps (the GPU sweep's own output, so both sides filter identical values)."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("window,ratio", [(5, 1.05), (3, 1.2), (7, 1.0)])
+def test_filter_matches_oracle(window, ratio):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+    wl = scenegen.workload("C1")
+    fr, st = wl.frames[0], wl.settings
+    ps = PlaneSweep(st, 320, 256, 1)
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    out = ps.alloc_outputs()
+    ps.run([frame_to_device(fr)], [out])
+    d, c = ps.filter(out["merged"], ratio_min=ratio, window=window)
+    torch.cuda.synchronize()
+    m = {k: v.cpu().numpy() for k, v in out["merged"].items()}
+    gd, gc = d.cpu().numpy(), c.cpu().numpy()
+    ps.close()
+    od, oc = oracle.depth_filter(fr.ref_cam, st.ground_n, m["depth"].astype(np.float64),
+                                 m["cost1"].astype(np.float64), m["cost2"].astype(np.float64),
+                                 ratio_min=ratio, window=window)
+    # decisions can differ only where an FP32 comparison sits on its threshold
+    near = np.abs(m["cost2"].astype(np.float64) - ratio * m["cost1"]) <= 1e-6 * np.abs(m["cost2"])
+    diff = (gc != oc) & ~near
+    print("codes", np.bincount(gc.ravel(), minlength=256)[[0, 1, 2, 3, 255]], "mismatch", diff.sum())
+    assert diff.sum() == 0
+    keep = (gc == 0) & (oc == 0)
+    assert np.array_equal(gd[keep], od[keep].astype(np.float32))
+    assert np.all(np.isnan(gd[gc != 0]))

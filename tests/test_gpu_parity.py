@@ -151,3 +151,25 @@ def test_two_levels_full_oracle():
     both = same & (rm["index"] == gm["index"])
     rel = np.abs(gm["depth"][both] - rm["depth"][both]) / rm["depth"][both]
     assert both.mean() > 0.3 and np.quantile(rel, 0.999) <= 1e-3
+
+
+def test_plane_chunks_bitwise_equal():
+    """Splitting the planes of every tile into chunks (combined afterwards)
+    gives bitwise the same maps as one pass over all planes."""
+    PlaneSweep, frame_to_device = _gpu()
+    fr = scenegen.random_small_frame(w=200, h=140, n_src=3, seed=12, f=120.0)
+    lv = Level(n_fronto=24, near=1.0, far=25.0, n_ground=12, h_lo=-0.4, h_hi=0.4, window=9)
+    st = Settings(levels=[lv], best_k=2)
+    maps = {}
+    for n in (1, 2, 3, 5, 8):
+        ps = PlaneSweep(st, 200, 140, 3)
+        ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+        ps.set_chunks(0, n)
+        out = ps.alloc_outputs()
+        ps.run([frame_to_device(fr)], [out])
+        torch.cuda.synchronize()
+        maps[n] = to_np(out["merged"])
+        ps.close()
+    for n in (2, 3, 5, 8):
+        for k in maps[1]:
+            assert np.array_equal(maps[1][k], maps[n][k], equal_nan=True), (n, k)

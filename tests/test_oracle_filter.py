@@ -1,0 +1,106 @@
+"""Pins of the oracle's depth-map filters (Sec. III-A, depth map filtering:
+best-cost threshold alpha per image part, first/second best cost ratio,
+local continuity with gamma = 0.5 m and delta = 0.3)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from scenegen import Camera
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+PAPER = dict(l.split() for l in open(os.path.join(GOLD, "paper_settings.txt")) if l.strip() and l[0] != "#")
+A_UP, A_LO = float(PAPER["alpha_upper"]), float(PAPER["alpha_lower"])
+GAMMA, DELTA = float(PAPER["gamma_m"]), float(PAPER["delta"])
+
+CAM = Camera(0.9, 20.0, 20.0, 15.5, 11.5, 32, 24)   # horizon between rows 11 and 12
+GN = (0.0, 1.0, 0.0)
+
+
+def _maps(depth=10.0, c1=0.02, c2=0.2):
+    return (np.full((24, 32), depth), np.full((24, 32), c1), np.full((24, 32), c2))
+
+
+def test_cost_threshold_per_image_part():
+    d, a, b = _maps(c1=0.1)         # above alpha_upper, below alpha_lower
+    _, code = oracle.depth_filter(CAM, GN, d, a, b, A_UP, A_LO, 1.05, GAMMA, DELTA, 5)
+    assert np.all(code[:12] == 1)   # upper part: 0.1 > 0.05
+    assert np.all(code[13:21, 3:29] == 0)
+    d, a, b = _maps(c1=0.31)
+    _, code = oracle.depth_filter(CAM, GN, d, a, b, A_UP, A_LO, 1.05, GAMMA, DELTA, 5)
+    assert np.all(code == 1)
+
+
+def test_uniqueness_ratio():
+    d, a, b = _maps(c1=0.02, c2=0.0205)   # ratio 1.025
+    _, code = oracle.depth_filter(CAM, GN, d, a, b, A_UP, A_LO, 1.05, GAMMA, DELTA, 5)
+    assert np.all(code == 2)
+    _, code = oracle.depth_filter(CAM, GN, d, a, b, A_UP, A_LO, 1.02, GAMMA, DELTA, 5)
+    assert np.all(code[3:21, 3:29] == 0)
+
+
+def test_continuity_and_invalid():
+    d, a, b = _maps()
+    d[16, 16] = 20.0                 # a spike: no neighbour within gamma
+    d[5, 5] = np.nan                 # invalid before filtering
+    out, code = oracle.depth_filter(CAM, GN, d, a, b, A_UP, A_LO, 1.05, GAMMA, DELTA, 5)
+    assert code[16, 16] == 3 and np.isnan(out[16, 16])
+    assert code[5, 5] == 255
+    assert code[16, 17] == 0 and out[16, 17] == 10.0
+    # a corner pixel sees only 8 of its 24 window neighbours: 8/24 = 0.33 >= 0.3
+    assert code[0, 0] == 0
+    # with delta = 0.4 the corner is rejected, an interior pixel is not
+    _, code = oracle.depth_filter(CAM, GN, d, a, b, A_UP, A_LO, 1.05, GAMMA, 0.4, 5)
+    assert code[0, 0] == 3 and code[12, 20] == 0
+
+
+def _brute_continuity(d1, gamma, delta, win):
+    h, w = d1.shape
+    hw = win // 2
+    pad = np.full((h + 2 * hw, w + 2 * hw), np.nan)
+    pad[hw:hw + h, hw:hw + w] = d1
+    cnt = np.zeros((h, w))
+    for dj in range(-hw, hw + 1):
+        for di in range(-hw, hw + 1):
+            if di == 0 and dj == 0:
+                continue
+            q = pad[hw + dj:hw + dj + h, hw + di:hw + di + w]
+            with np.errstate(invalid="ignore"):
+                cnt += (np.abs(q - d1) < gamma)
+    return np.isfinite(d1) & (cnt >= delta * (win * win - 1))
+
+
+@pytest.mark.parametrize("win", [3, 5, 7])
+def test_continuity_brute_force(win):
+    rng = np.random.default_rng(win)
+    d = rng.choice([5.0, 5.3, 5.9, 8.0], size=(24, 32)) + rng.normal(0, 0.05, (24, 32))
+    d[rng.random((24, 32)) < 0.1] = np.nan
+    a = np.full_like(d, 0.02)
+    b = np.full_like(d, 0.2)
+    out, code = oracle.depth_filter(CAM, GN, d, a, b, A_UP, A_LO, 1.05, GAMMA, DELTA, win)
+    keep = _brute_continuity(d, GAMMA, DELTA, win)
+    assert np.array_equal(keep, code == 0)
+    assert np.array_equal(np.isfinite(out), keep)
+
+
+@pytest.mark.slow
+def test_filters_reduce_error_on_a_scene():
+    """Sec. IV-B: after the filters the median and mean depth errors drop
+    (the paper reports more than 40% and 60%).  On the C1 scene the filtered
+    map's errors against the renderer's ground truth are lower."""
+    wl = scenegen.workload("C1")
+    fr, st = wl.frames[0], wl.settings
+    res = oracle.run(fr, st)["merged"]
+    out, code = oracle.depth_filter(fr.ref_cam, st.ground_n, res["depth"], res["cost1"], res["cost2"])
+    gt = fr.gt_range
+    raw = np.isfinite(res["depth"]) & np.isfinite(gt)
+    flt = np.isfinite(out) & np.isfinite(gt)
+    e_raw = np.abs(res["depth"][raw] - gt[raw])
+    e_flt = np.abs(out[flt] - gt[flt])
+    print("raw mean/median", e_raw.mean(), np.median(e_raw), "filtered", e_flt.mean(), np.median(e_flt),
+          "kept", flt.sum() / raw.sum())
+    assert e_flt.mean() < 0.7 * e_raw.mean()
+    assert np.median(e_flt) < np.median(e_raw)
+    assert flt.sum() > 0.3 * raw.sum()
