@@ -60,6 +60,73 @@ def cpu_baseline(fr, st, target_s=15.0):
                       f"FP64 two-pass ZNCC per window ({dt2:.1f} s)"}
 
 
+def bench_c5(args):
+    """C5: 16 frame sets of mixed size (1280x960 / 1024x768 / 640x480), 4
+    sources, two levels of 192 + 64 planes.  The batched form (one
+    persistent launch for every frame, level and tile, FP16 staging, replayed
+    as a HIP graph) against plain per-frame FP32 launches."""
+    import torch
+
+    import scenegen
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+
+    wl = scenegen.workload("C5")
+    frames = wl.frames
+    W, H = scenegen.C5_SIZES[0]
+    st = scenegen.c5_settings(W, H)
+    dev = []
+    for i, fr in enumerate(frames):
+        d = frame_to_device(fr)
+        d["camera_set"] = i
+        dev.append(d)
+
+    def setup(ps):
+        for i, fr in enumerate(frames):
+            ps.set_cameras(i, fr.ref_cam, fr.src_cams, fr.poses)
+            w, h = fr.ref_cam.width, fr.ref_cam.height
+            ps.set_crop(i, (w - w // 2) // 2, (h - h // 2) // 2, w // 2, h // 2)
+
+    res = {}
+    # plain: one frame per run, FP32 staging, per-level grid launches
+    ps = PlaneSweep(st, W, H, 4, max_frames=1, max_camera_sets=len(frames), storage="f32", launch="grid")
+    setup(ps)
+    outs = [ps.alloc_outputs(camera_set=i) for i in range(len(frames))]
+    pp = sum(ps.plane_pixels([d]) for d in dev)
+    for _ in range(args.warmup):
+        for d, o in zip(dev, outs):
+            ps.run([d], [o])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for d, o in zip(dev, outs):
+            ps.run([d], [o])
+    torch.cuda.synchronize()
+    res["plain_f32_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
+    ps.close()
+    # batched: all frames in one persistent launch, FP16 staging, HIP graph
+    for storage in ("f16", "f32"):
+        ps = PlaneSweep(st, W, H, 4, max_frames=len(frames), max_camera_sets=len(frames), storage=storage,
+                        launch="persistent")
+        setup(ps)
+        outs = [ps.alloc_outputs(camera_set=i) for i in range(len(frames))]
+        ps.capture_graph(dev, outs)
+        for _ in range(args.warmup):
+            ps.launch_graph()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ps.launch_graph()
+        torch.cuda.synchronize()
+        res[f"batched_{storage}_graph_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
+        ps.close()
+    line = {"metric": METRIC, "workload": "C5", "plane_pixels_per_batch": pp, "maps_per_batch": len(frames)}
+    for k, v in res.items():
+        line[k] = v
+        line[k.replace("_ms", "_gpps")] = pp / (v * 1e-3) / 1e9
+    line["batched_f16_vs_plain_f32"] = res["plain_f32_ms"] / res["batched_f16_graph_ms"]
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +134,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--workload", default="C2", choices=["C2", "C5"],
+                    help="C2 (default): the benchmark line; C5: batched vs plain comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -74,6 +143,10 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build sweeps on one "
               "device; see the sharding notes)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "C5":
+        bench_c5(args)
+        return
 
     import torch
 

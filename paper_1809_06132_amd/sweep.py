@@ -183,6 +183,10 @@ class PlaneSweep:
         pf = [self._frame(f) for f in frames]
         po = [self._output(o) for o in outputs]
         P.psweep_run(self.ctx, pf, po, _stream_handle(stream))
+        if self.settings.mode == "soft":
+            # the backward re-reads the reference image of this run: hold the
+            # tensors so the caching allocator cannot hand their memory out
+            self._soft_frames = list(frames)
 
     def capture_graph(self, frames, outputs, stream=None):
         pf = [self._frame(f) for f in frames]

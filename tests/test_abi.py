@@ -78,3 +78,17 @@ def test_null_arguments():
     assert L.psweep_workspace_size(None, None) == psweep.EINVAL
     assert L.psweep_run(None, None, 0, None, None) == psweep.EINVAL
     assert L.psweep_soft_depth_backward(None, None, None, None, None) == psweep.EINVAL
+
+
+def test_product_path_is_independent_of_the_oracle():
+    """The package never imports, loads or calls the oracle, and the oracle
+    never includes the GPU sources: the two share no code."""
+    pkg = os.path.join(ROOT, "paper_1809_06132_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "liboracle" not in text and "or_sweep" not in text, f
+    otext = open(os.path.join(ROOT, "oracle", "psweep_oracle.c")).read()
+    assert "#include \"" not in otext and "psw::" not in otext
+    assert "paper_1809_06132_amd" not in open(os.path.join(ROOT, "oracle", "__init__.py")).read()
