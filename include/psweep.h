@@ -194,9 +194,11 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
 psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_invdepth,
                                          float *const *d_grad_src, double *d_grad_pose, void *hip_stream);
 
-/* Tile shape of the sweep kernel for one level: rows per wave (8 or 16)
- * and waves per workgroup (2 or 4); 0 restores the default.  Used by the
- * autotuner.  EINVAL for other values. */
+/* Tile shape of the sweep kernel for one level: rows per wave (2, 4, 8 or
+ * 16) and waves per workgroup (2, 4 or 8); 0, 0 restores the default.  Used
+ * by the autotuner.  EINVAL for other values; psweep_run returns
+ * EUNSUPPORTED when no kernel is built for the shape with the level's
+ * window, source count and storage. */
 psweep_status psweep_set_tile(psweep_ctx *ctx, int32_t level, int32_t rows_per_wave, int32_t waves);
 
 /* Depth-map filtering parameters (Sec. III-A): the best-cost threshold for

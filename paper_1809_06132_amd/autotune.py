@@ -14,7 +14,7 @@ import torch
 
 from .sweep import PlaneSweep
 
-CANDIDATES = [(8, 4), (16, 4), (8, 2)]
+CANDIDATES = [(4, 4), (8, 4), (4, 8), (2, 8), (16, 4), (8, 2)]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "psweep_tiles.json")
 
 

@@ -76,6 +76,10 @@ void load_tables() {
     g_all.insert(g_all.end(), t, t + n);
     n = psw_kernels_extra(&t);
     g_all.insert(g_all.end(), t, t + n);
+    n = psw_kernels_small(&t);
+    g_all.insert(g_all.end(), t, t + n);
+    n = psw_kernels_grid8(&t);
+    g_all.insert(g_all.end(), t, t + n);
     n = psw_kernels_persistent(&t);
     g_all.insert(g_all.end(), t, t + n);
     g_entries = g_all.data();
@@ -115,7 +119,7 @@ struct psweep_ctx {
     int staging_idx = 0;
     std::vector<char> last_table;
     uint64_t cam_version = 1, setup_version = 0;
-    int tile_rows[PSWEEP_MAX_LEVELS] = {8, 8}, tile_waves[PSWEEP_MAX_LEVELS] = {4, 4};
+    int tile_rows[PSWEEP_MAX_LEVELS] = {4, 4}, tile_waves[PSWEEP_MAX_LEVELS] = {4, 4};
     int chunks[PSWEEP_MAX_LEVELS] = {0, 0};   // plane chunks per tile; 0 = automatic
     int n_cu = 256;
     size_t s_part[PSWEEP_MAX_LEVELS] = {0, 0};
@@ -356,9 +360,10 @@ psweep_status psweep_set_crop(psweep_ctx *ctx, int32_t camera_set, int32_t x, in
 psweep_status psweep_set_tile(psweep_ctx *ctx, int32_t level, int32_t rows_per_wave, int32_t waves) {
     if (!ctx) return PSWEEP_EINVAL;
     if (level < 0 || level >= ctx->cfg.n_levels) return fail(ctx, PSWEEP_EINVAL, "level out of range");
-    if (rows_per_wave == 0 && waves == 0) { rows_per_wave = 8; waves = 4; }
-    if ((rows_per_wave != 8 && rows_per_wave != 16) || (waves != 2 && waves != 4))
-        return fail(ctx, PSWEEP_EINVAL, "rows_per_wave must be 8 or 16 and waves 2 or 4");
+    if (rows_per_wave == 0 && waves == 0) { rows_per_wave = 4; waves = 4; }
+    const bool rows_ok = rows_per_wave == 2 || rows_per_wave == 4 || rows_per_wave == 8 || rows_per_wave == 16;
+    if (!rows_ok || (waves != 2 && waves != 4 && waves != 8))
+        return fail(ctx, PSWEEP_EINVAL, "rows_per_wave must be 2, 4, 8 or 16 and waves 2, 4 or 8");
     ctx->tile_rows[level] = rows_per_wave;
     ctx->tile_waves[level] = waves;
     return PSWEEP_OK;
@@ -508,13 +513,13 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             J.tiles_x = rc.w > 2 * hw ? (rc.w - 2 * hw + TXO - 1) / TXO : 0;
             J.tiles_y = rc.h > 2 * hw ? (rc.h - 2 * hw + TYO - 1) / TYO : 0;
             J.rows = rows; J.waves = waves;
-            // plane chunks: enough workgroups for about ten waves per SIMD over
-            // the launch, so that uneven tiles still balance
+            // plane chunks: enough workgroups for about twenty waves per SIMD
+            // over the launch, so that uneven tiles still balance
             {
                 const int ntile = J.tiles_x * J.tiles_y;
                 int nch = ctx->chunks[l];
                 if (nch == 0) {
-                    const long long target = 10LL * ctx->n_cu * 4;
+                    const long long target = 20LL * ctx->n_cu * 4;
                     const long long have = (long long)ntile * waves * (cfg.launch == PSWEEP_LAUNCH_PERSISTENT ? nf : 1);
                     nch = have > 0 ? (int)((target + have - 1) / have) : 1;
                     nch = std::max(1, std::min(nch, kMaxChunks));
@@ -673,13 +678,14 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
     if (cfg.launch == PSWEEP_LAUNCH_GRID) {
         for (int j = 0; j < nj; ++j) {
             const JobDev &J = (*host_jobs)[j];
-            const int nt = J.tiles_x * J.tiles_y * std::max(1, J.nch_f + J.nch_g);
-            if (nt == 0) continue;
+            const int ntile = J.tiles_x * J.tiles_y;
+            if (ntile == 0) continue;
             const KernelEntry *e = find_kernel(J.window, J.rows, J.waves, J.n_src, store, soft, 0);
             if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no kernel for this window/tile/sources/storage");
             JobDev *jp = dj + j;
             void *a[] = {&jp};
-            const int grid = 8 * ((nt + 7) / 8);
+            // blocks x, x + 8, ... sweep tile rows x, x + 8, ... chunk by chunk
+            const int grid = 8 * ((J.tiles_y + 7) / 8) * J.tiles_x * std::max(1, J.nch_f + J.nch_g);
             if (timed) PSW_HIP(hipEventRecord(ctx->ev0[ctx->n_timed], stream), "event record");
             PSW_HIP(hipLaunchKernel(e->fn, dim3(grid), dim3(kWave * J.waves), a, e->lds, stream), "sweep");
             if (timed) PSW_HIP(hipEventRecord(ctx->ev1[ctx->n_timed++], stream), "event record");

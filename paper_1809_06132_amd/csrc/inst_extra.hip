@@ -1,4 +1,4 @@
-// Half-precision staging, alternative tile shapes and the soft-argmin sweep.
+// Half-precision staging and the soft-argmin sweep, default tile (4 x 4).
 #include "sweep_common.h"
 
 namespace psw {
@@ -9,13 +9,9 @@ namespace psw {
     PSW_E(W, R, NW, 1, ST, SOFT), PSW_E(W, R, NW, 2, ST, SOFT), PSW_E(W, R, NW, 3, ST, SOFT), PSW_E(W, R, NW, 4, ST, SOFT)
 static const KernelEntry kExtra[] = {
     // FP16 / BF16 staging
-    PSW_S4(7, 8, 4, 1, false), PSW_S4(9, 8, 4, 1, false), PSW_S4(7, 8, 4, 2, false), PSW_S4(9, 8, 4, 2, false),
-    // tile shapes for the autotuner
-    PSW_E(7, 16, 4, 3, 0, false), PSW_E(9, 16, 4, 3, 0, false), PSW_E(7, 16, 4, 4, 0, false), PSW_E(9, 16, 4, 4, 0, false),
-    PSW_E(7, 8, 2, 3, 0, false), PSW_E(9, 8, 2, 3, 0, false), PSW_E(7, 8, 2, 4, 0, false), PSW_E(9, 8, 2, 4, 0, false),
-    PSW_E(7, 16, 4, 4, 1, false), PSW_E(9, 16, 4, 4, 1, false), PSW_E(7, 8, 2, 4, 1, false), PSW_E(9, 8, 2, 4, 1, false),
+    PSW_S4(7, 4, 4, 1, false), PSW_S4(9, 4, 4, 1, false), PSW_S4(7, 4, 4, 2, false), PSW_S4(9, 4, 4, 2, false),
     // soft-argmin
-    PSW_S4(5, 8, 4, 0, true), PSW_S4(7, 8, 4, 0, true), PSW_S4(9, 8, 4, 0, true),
+    PSW_S4(5, 4, 4, 0, true), PSW_S4(7, 4, 4, 0, true), PSW_S4(9, 4, 4, 0, true),
 };
 }  // namespace psw
 

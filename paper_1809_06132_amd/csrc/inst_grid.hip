@@ -1,4 +1,4 @@
-// Plain per-level sweep launches, FP32 staging, default tile (8 rows x 4 waves).
+// Plain per-level sweep launches, FP32 staging, default tile (4 rows x 4 waves).
 #include "sweep_common.h"
 
 namespace psw {
@@ -8,8 +8,8 @@ namespace psw {
 #define PSW_S4(W, R, NW, ST, SOFT) \
     PSW_E(W, R, NW, 1, ST, SOFT), PSW_E(W, R, NW, 2, ST, SOFT), PSW_E(W, R, NW, 3, ST, SOFT), PSW_E(W, R, NW, 4, ST, SOFT)
 static const KernelEntry kGrid[] = {
-    PSW_S4(3, 8, 4, 0, false),  PSW_S4(5, 8, 4, 0, false),  PSW_S4(7, 8, 4, 0, false), PSW_S4(9, 8, 4, 0, false),
-    PSW_S4(11, 8, 4, 0, false), PSW_S4(13, 8, 4, 0, false), PSW_S4(15, 8, 4, 0, false),
+    PSW_S4(3, 4, 4, 0, false),  PSW_S4(5, 4, 4, 0, false),  PSW_S4(7, 4, 4, 0, false), PSW_S4(9, 4, 4, 0, false),
+    PSW_S4(11, 4, 4, 0, false), PSW_S4(13, 4, 4, 0, false), PSW_S4(15, 4, 4, 0, false),
 };
 }  // namespace psw
 

@@ -12,7 +12,7 @@ constexpr size_t persistent_lds() {
 #define PSW_P(R, NW, S, ST) {0, R, NW, S, ST, 0, 1, (const void *)&sweep_persistent_kernel<R, NW, S, ST>, persistent_lds<R, NW, S, ST>()}
 #define PSW_P4(R, NW, ST) PSW_P(R, NW, 1, ST), PSW_P(R, NW, 2, ST), PSW_P(R, NW, 3, ST), PSW_P(R, NW, 4, ST)
 static const KernelEntry kPersistent[] = {
-    PSW_P4(8, 4, 0), PSW_P4(8, 4, 1), PSW_P4(8, 4, 2), PSW_P(8, 2, 4, 1),
+    PSW_P4(4, 4, 0), PSW_P4(4, 4, 1), PSW_P4(4, 4, 2), PSW_P4(8, 4, 0), PSW_P(8, 4, 4, 1),
 };
 }  // namespace psw
 

@@ -167,4 +167,6 @@ struct KernelEntry {
 // Each instantiation unit exports its table through one of these.
 extern "C" int psw_kernels_grid(const psw::KernelEntry **out);
 extern "C" int psw_kernels_extra(const psw::KernelEntry **out);
+extern "C" int psw_kernels_small(const psw::KernelEntry **out);
+extern "C" int psw_kernels_grid8(const psw::KernelEntry **out);
 extern "C" int psw_kernels_persistent(const psw::KernelEntry **out);

@@ -480,22 +480,26 @@ struct Tile {
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
-// One grid per (frame, level): blockIdx.x enumerates tiles; consecutive
-// blocks go to different XCDs, so block b is given tile (b % 8) * per + b / 8
-// and every XCD sweeps a contiguous band of the image (its L2 then holds the
-// band's source texels).
+// One grid per (frame, level).  Workgroups go to the eight XCDs in turn
+// (block b to XCD b % 8), so XCD x runs blocks x, x + 8, ...: it is given the
+// tile rows x, x + 8, x + 16, ... of the image and sweeps them one plane
+// chunk after another.  Every XCD so holds an equal share of the image's
+// upper and lower parts (ground-plane chunks cost little above the horizon),
+// and its resident workgroups sweep the same planes over nearby tiles.
 template <int WIN, int R, int NW, int S, int STORE, bool SOFT>
 __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__restrict__ job) {
     extern __shared__ char smem[];
-    const int ntile = job->tiles_x * job->tiles_y;
     const int nch = job->nch_f + job->nch_g;
-    const int nt = ntile * (nch > 1 ? nch : 1);
-    const int per = (nt + 7) / 8;
-    const int b = blockIdx.x;
-    const int t = (b & 7) * per + (b >> 3);
-    if (t >= nt) return;
-    const int tile = t % ntile, chunk = t / ntile;
-    Tile<WIN, R, NW, S, STORE, SOFT>::run(job, tile % job->tiles_x, tile / job->tiles_x, chunk, smem);
+    const int nc = nch > 1 ? nch : 1;
+    const int tx = job->tiles_x, ty = job->tiles_y;
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
+    const int nrows = ty > x ? (ty - x + 7) / 8 : 0;     // tile rows of XCD x
+    const int per_chunk = nrows * tx;
+    if (i >= per_chunk * nc) return;
+    const int chunk = i / per_chunk;
+    const int r = i - chunk * per_chunk;
+    const int tile_y = x + 8 * (r / tx);
+    Tile<WIN, R, NW, S, STORE, SOFT>::run(job, r % tx, tile_y, chunk, smem);
 }
 
 // One persistent launch for every (frame, level, tile) of a run: workgroups

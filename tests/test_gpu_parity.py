@@ -80,7 +80,7 @@ def test_small_ragged_full_oracle(case):
     assert np.quantile(np.abs(g["delta"][same] - ref["delta"][same]), 0.999) <= 5e-3
 
 
-@pytest.mark.parametrize("tile", [(8, 4), (16, 4), (8, 2)])
+@pytest.mark.parametrize("tile", [(8, 4), (16, 4), (8, 2), (4, 8), (4, 4), (2, 8)])
 def test_tile_shapes_agree(tile):
     fr = scenegen.random_small_frame(w=150, h=90, n_src=3, seed=8, f=90.0)
     lv = Level(n_fronto=10, near=1.0, far=25.0, n_ground=6, h_lo=-0.4, h_hi=0.4, window=9)
