@@ -98,12 +98,19 @@ __device__ __forceinline__ T window_sum(T v, const Shifts &sh, SHR1 s1, FROM fro
     T b2 = v + s1(v);
     T b4 = (WIN >= 5) ? b2 + from(b2, sh.at(2)) : b2;
     T b8 = (WIN >= 9) ? b4 + from(b4, sh.at(4)) : b4;
-    T acc = 0;
+    // the first block placed starts the sum (0 + x is not free: it turns -0
+    // into +0, so the compiler keeps the add)
+    T acc;
+    bool first = true;
     int pos = h;   // right end of the uncovered part, relative to l
-    if (WIN & 8) { acc += from(b8, sh.at(-pos)); pos -= 8; }
-    if (WIN & 4) { acc += from(b4, sh.at(-pos)); pos -= 4; }
-    if (WIN & 2) { acc += from(b2, sh.at(-pos)); pos -= 2; }
-    if (WIN & 1) { acc += (pos == 0) ? b1 : from(b1, sh.at(-pos)); }
+    auto put = [&](T blk) {
+        acc = first ? blk : acc + blk;
+        first = false;
+    };
+    if (WIN & 8) { put(from(b8, sh.at(-pos))); pos -= 8; }
+    if (WIN & 4) { put(from(b4, sh.at(-pos))); pos -= 4; }
+    if (WIN & 2) { put(from(b2, sh.at(-pos))); pos -= 2; }
+    if (WIN & 1) { put((pos == 0) ? b1 : from(b1, sh.at(-pos))); }
     return acc;
 }
 template <int WIN>
@@ -393,9 +400,13 @@ struct Tile {
                         const ST *cs = col + (size_t)s * T * kWave;
                         const float b = St::get(cs[(size_t)m * kWave]);
                         last_bad[s] = is_neg_zero(b) ? m : last_bad[s];
-                        vb[s] += b;
-                        vbb[s] = fmaf(b, b, vbb[s]);
-                        vab[s] = fmaf(av[m], b, vab[s]);
+                        if (m == 0) {   // start the sums with the first row (no 0 + x)
+                            vb[s] = b; vbb[s] = b * b; vab[s] = av[m] * b;
+                        } else {
+                            vb[s] += b;
+                            vbb[s] = fmaf(b, b, vbb[s]);
+                            vab[s] = fmaf(av[m], b, vab[s]);
+                        }
                         if (m >= WIN) {
                             const float bo = St::get(cs[(size_t)(m - WIN) * kWave]);
                             vb[s] -= bo;
