@@ -35,6 +35,38 @@ def algorithmic_ops_per_plane_pixel(n_src: int) -> int:
     return 60 * n_src + 6
 
 
+# HBM bytes per launch of the sweep kernel on the C2 workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+# "python bench.py --steps 2 --warmup 1 --no-cpu --copy-calibration", each
+# scaled by what the same counter reads for a 256 MiB device copy (FETCH_SIZE
+# reads half the copied bytes, WRITE_SIZE all of them).  Valid only for the
+# kernel sources they were taken on: a source hash guards them.
+COUNTED_TRAFFIC = {
+    "sources_sha256": "35438face1be3c65909402917e3f40f7f6dcfc10d1fdb946e3f303a800b29b49",
+    "fetch_kib": 20548.2, "write_kib": 134930.0, "fetch_scale": 262144.0 / 131084.0, "write_scale": 1.0,
+}
+TRAFFIC_SOURCES = ["paper_1809_06132_amd/csrc/sweep_common.h", "paper_1809_06132_amd/csrc/psweep_internal.h",
+                   "paper_1809_06132_amd/csrc/inst_grid.hip", "paper_1809_06132_amd/csrc/api.cpp"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counted_traffic():
+    """HBM bytes per sweep launch from the counters, or None when the kernel
+    sources changed since they were taken."""
+    c = COUNTED_TRAFFIC
+    if c["sources_sha256"] is None or c["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
+
+
 def cpu_baseline(fr, st, target_s=15.0):
     import numpy as np
 
@@ -54,7 +86,7 @@ def cpu_baseline(fr, st, target_s=15.0):
     t0 = time.perf_counter()
     oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=sample(n2))
     dt2 = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.threads()
     return {"value": n2 * P / dt2 / 1e9, "unit": "Gpix·planes/s", "cores": cores, "kind": "oracle",
             "sample": f"{n2} random pixels of the 1024x768 frame, all {P} planes x 3 sources, "
                       f"FP64 two-pass ZNCC per window ({dt2:.1f} s)"}
@@ -170,6 +202,19 @@ def main():
     elapsed = time.perf_counter() - t0
     ms = elapsed / args.steps * 1e3
 
+    # distribution of single steps (HIP events on the launch stream, which is
+    # torch's current stream here), after the timed region
+    import numpy as np
+    step_ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ps.run([frame], [out])
+        e1.record()
+        torch.cuda.synchronize()
+        step_ms.append(e0.elapsed_time(e1))
+    p10, p50, p90 = (float(v) for v in np.percentile(step_ms, [10, 50, 90]))
+
     # sweep-kernel duration from HIP events recorded on the launch stream
     ps.set_timing(True)
     kms = []
@@ -190,6 +235,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "step_ms_p10_p50_p90": [p10, p50, p90],
         "maps_per_s": 1e3 / ms,
         "higher_is_better": True,
         "scaling": "weak",
@@ -200,7 +246,7 @@ def main():
                                "ZNCC 9x9, mean of best 2, WTA + parabola",
                    "plane_pixels_per_step": plane_pixels, "launch": "grid", "storage": args.storage},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-ops/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": counted_traffic(),
                      "kernel_ms": kernel_ms,
                      "ops_per_plane_pixel": algorithmic_ops_per_plane_pixel(len(fr.srcs))},
     }

@@ -97,6 +97,8 @@ def lib():
     L.or_soft_backward.restype = None
     L.or_filter.argtypes = [PC, _p, _i32, _i32, _p, _p, _p, _d, _d, _d, _d, _d, _i32, _p, _p]
     L.or_filter.restype = None
+    L.or_threads.argtypes = []
+    L.or_threads.restype = _i32
     return L
 
 
@@ -400,3 +402,8 @@ def depth_filter(cam, ground_n, depth, cost1, cost2, alpha_upper=0.05, alpha_low
                     float(alpha_upper), float(alpha_lower), float(ratio_min), float(gamma), float(delta),
                     int(window), out.ctypes.data, code.ctypes.data)
     return out, code
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_threads())

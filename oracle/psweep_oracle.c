@@ -25,6 +25,7 @@
  * Every window is evaluated from scratch: each sample is warped on its own and
  * the ZNCC is the textbook two-pass formula (means first, then centred sums).
  */
+#include <omp.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -665,3 +666,6 @@ void or_filter(const or_camera *cam, const double ground_n[3], int32_t w, int32_
         }
     free(d1);
 }
+
+/* Threads the parallel loops above use (for reporting the baseline's cores). */
+int or_threads(void) { return omp_get_max_threads(); }
