@@ -66,6 +66,10 @@ typedef enum {
 enum { PSWEEP_STORAGE_F32 = 0, PSWEEP_STORAGE_F16 = 1, PSWEEP_STORAGE_BF16 = 2 };
 enum { PSWEEP_MODE_WTA = 0, PSWEEP_MODE_SOFT = 1 };
 enum { PSWEEP_LAUNCH_GRID = 0, PSWEEP_LAUNCH_PERSISTENT = 1 };
+/* Pixel type of the frame images: 8-bit grey levels, or 32-bit float grey
+ * values (any real values; the cost is invariant to affine intensity changes
+ * but the variance floor is in grey levels squared). */
+enum { PSWEEP_IMAGE_U8 = 0, PSWEEP_IMAGE_F32 = 1 };
 
 typedef struct psweep_ctx psweep_ctx;
 
@@ -113,13 +117,17 @@ typedef struct {
     int32_t max_sources;            /* <= PSWEEP_MAX_SOURCES */
     int32_t max_frames;             /* frames per psweep_run */
     int32_t max_camera_sets;
+    int32_t image_format;           /* PSWEEP_IMAGE_U8 or PSWEEP_IMAGE_F32 (F32: one level, no
+                                       downsample or crop, grid launch) */
 } psweep_config;
 
-/* One frame set: device images and the camera set describing them. */
+/* One frame set: device images and the camera set describing them.  The
+ * pointers are uint8_t or float images as the config's image_format says,
+ * row-major; pitches in elements (pixels), not bytes. */
 typedef struct {
-    const uint8_t *ref;
+    const void *ref;
     int64_t ref_pitch;
-    const uint8_t *src[PSWEEP_MAX_SOURCES];
+    const void *src[PSWEEP_MAX_SOURCES];
     int64_t src_pitch[PSWEEP_MAX_SOURCES];
     int32_t camera_set;
 } psweep_frame;
@@ -147,9 +155,11 @@ typedef struct {
 
 /* Create a context for `cfg`.  EINVAL on inconsistent settings (even window,
  * fewer than 2 planes in a used family, non-positive plane distances, sizes
- * or counts out of range, best_k outside [1, max_sources]); EUNSUPPORTED for
- * soft mode with ground planes, with two levels, with a downsampled or
- * cropped level or with the persistent launch.  *out receives the context. */
+ * or counts out of range, best_k outside [1, max_sources], unknown
+ * image_format); EUNSUPPORTED for soft mode with ground planes, with two
+ * levels, with a downsampled or cropped level or with the persistent launch,
+ * and for float images with anything but one full-resolution level on the
+ * grid launch.  *out receives the context. */
 psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out);
 
 /* Bytes of device workspace the context needs (fixed by the config). */

@@ -12,8 +12,10 @@ returned gradient is the library's left-perturbation gradient, exact at
 xi = 0 (the usual use: re-linearise after every update).
 
 Sources may be uint8 (no image gradient) or float tensors holding grey
-values; float images are rounded to 8 bits for the forward and receive the
-gradient of the interpolated intensities (straight-through rounding)."""
+values.  A sweep built with image_format="f32" sweeps float images as they
+are and returns their exact gradient; one built for 8-bit images rounds
+float sources to 8 bits for the forward and returns the gradient of the
+interpolated intensities (straight-through rounding)."""
 from __future__ import annotations
 
 import math
@@ -53,7 +55,11 @@ class SoftDepth(torch.autograd.Function):
         xi = pose_xi.detach().to("cpu", torch.float64).numpy()
         poses = [_Pose(*perturb_pose(np.asarray(p.R), np.asarray(p.t), xi[s])) for s, p in enumerate(base)]
         sweep.set_cameras(0, ref_cam, src_cams, poses)
-        u8 = [s if s.dtype == torch.uint8 else s.detach().round().clamp(0, 255).to(torch.uint8) for s in srcs]
+        if sweep.image_dtype == torch.float32:
+            u8 = [s.detach().float().contiguous() for s in srcs]
+            ref = ref.detach().float().contiguous()
+        else:
+            u8 = [s if s.dtype == torch.uint8 else s.detach().round().clamp(0, 255).to(torch.uint8) for s in srcs]
         out = sweep.alloc_outputs()
         sweep.run([{"ref": ref, "srcs": u8, "camera_set": 0}], [out])
         ctx.sweep = sweep

@@ -23,7 +23,7 @@ extern "C" const void *psw_reset_kernel();
 extern "C" const void *psw_merge_kernel();
 extern "C" const void *psw_chunk_merge_kernel();
 extern "C" const void *psw_filter_kernel();
-extern "C" const void *psw_backward_kernel(int win, int n_src);
+extern "C" const void *psw_backward_kernel(int win, int n_src, int img);
 extern "C" size_t psw_backward_lds(int win, int n_src);
 extern "C" const void *psw_zero_kernel();
 
@@ -80,18 +80,21 @@ void load_tables() {
     g_all.insert(g_all.end(), t, t + n);
     n = psw_kernels_grid8(&t);
     g_all.insert(g_all.end(), t, t + n);
+    n = psw_kernels_f32img(&t);
+    g_all.insert(g_all.end(), t, t + n);
     n = psw_kernels_persistent(&t);
     g_all.insert(g_all.end(), t, t + n);
     g_entries = g_all.data();
     g_n_entries = (int)g_all.size();
 }
 
-const KernelEntry *find_kernel(int win, int rows, int waves, int n_src, int store, int soft, int persistent) {
+const KernelEntry *find_kernel(int win, int rows, int waves, int n_src, int store, int soft, int persistent,
+                               int img) {
     load_tables();
     for (int i = 0; i < g_n_entries; ++i) {
         const KernelEntry &e = g_entries[i];
         if (e.persistent == persistent && e.rows == rows && e.waves == waves && e.n_src == n_src &&
-            e.store == store && e.soft == soft && (persistent || e.win == win))
+            e.store == store && e.soft == soft && e.img == img && (persistent || e.win == win))
             return &e;
     }
     return nullptr;
@@ -159,6 +162,9 @@ psweep_status hip_fail(psweep_ctx *c, hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
     } while (0)
 
+// bytes of one quad-packed source texel: 4 x u8, or 4 x float
+size_t texel_bytes(const psweep_config &c) { return c.image_format == PSWEEP_IMAGE_F32 ? 16 : 4; }
+
 bool single_full(const psweep_config &c) {
     return c.n_levels == 1 && c.level[0].downsample == 1 && c.level[0].crop_w == 0;
 }
@@ -176,6 +182,7 @@ psweep_status check_config(const psweep_config *c) {
     if (c->storage < 0 || c->storage > 2) return bad("storage must be F32, F16 or BF16");
     if (c->mode != PSWEEP_MODE_WTA && c->mode != PSWEEP_MODE_SOFT) return bad("mode must be WTA or SOFT");
     if (c->launch != PSWEEP_LAUNCH_GRID && c->launch != PSWEEP_LAUNCH_PERSISTENT) return bad("bad launch kind");
+    if (c->image_format != PSWEEP_IMAGE_U8 && c->image_format != PSWEEP_IMAGE_F32) return bad("bad image_format");
     const double gn = std::sqrt(c->ground_n[0] * c->ground_n[0] + c->ground_n[1] * c->ground_n[1] +
                                 c->ground_n[2] * c->ground_n[2]);
     for (int l = 0; l < c->n_levels; ++l) {
@@ -208,6 +215,12 @@ psweep_status check_config(const psweep_config *c) {
         if (c->launch != PSWEEP_LAUNCH_GRID) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode uses the grid launch");
         if (c->storage != PSWEEP_STORAGE_F32) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode stages in FP32");
         if (!(c->temperature > 0.0)) return bad("temperature must be > 0");
+    }
+    if (c->image_format == PSWEEP_IMAGE_F32) {
+        if (!single_full(*c))
+            return fail(nullptr, PSWEEP_EUNSUPPORTED, "float images need one full-resolution level");
+        if (c->launch != PSWEEP_LAUNCH_GRID) return fail(nullptr, PSWEEP_EUNSUPPORTED, "float images use the grid launch");
+        if (c->storage != PSWEEP_STORAGE_F32) return fail(nullptr, PSWEEP_EUNSUPPORTED, "float images stage in FP32");
     }
     if (c->launch == PSWEEP_LAUNCH_PERSISTENT) {
         for (int l = 0; l < c->n_levels; ++l)
@@ -266,7 +279,7 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
         const size_t rpx = (size_t)ctx->ref_w[l] * ctx->ref_h[l];
         const size_t spx = (size_t)ctx->src_w[l] * ctx->src_h[l];
         ctx->s_ref[l] = so;   so += align_up(rpx);
-        ctx->s_tex[l] = so;   so += align_up(spx * 4) * S;
+        ctx->s_tex[l] = so;   so += align_up(spx * texel_bytes(*cfg)) * S;
         ctx->s_maps[l] = so;  so += align_up(rpx * 4) * 4;
         ctx->s_htab[l] = so;  so += align_up((size_t)ctx->P[l] * S * 9 * 4);
         ctx->s_theta[l] = so; so += align_up((size_t)ctx->P[l] * 4);
@@ -463,7 +476,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
                 J.ref = (const uint8_t *)(slot + ctx->s_ref[l]);
                 J.ref_pitch = C.ref.width / 2;
             } else {
-                J.ref = fr.ref + (l == 1 ? (int64_t)crop_y * fr.ref_pitch + crop_x : 0);
+                J.ref = (const uint8_t *)fr.ref + (l == 1 ? (int64_t)crop_y * fr.ref_pitch + crop_x : 0);
                 J.ref_pitch = fr.ref_pitch;
             }
             J.w = rc.w; J.h = rc.h;
@@ -541,7 +554,8 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             for (int s = 0; s < C.n_src; ++s) {
                 const LevelCam sc = level_cam(C.src[s], ds, 0, 0, 0, 0);
                 SrcDev &D = J.src[s];
-                D.tex = (const uint32_t *)(slot + ctx->s_tex[l] + align_up((size_t)ctx->src_w[l] * ctx->src_h[l] * 4) * s);
+                D.tex = (const uint32_t *)(slot + ctx->s_tex[l] +
+                                           align_up((size_t)ctx->src_w[l] * ctx->src_h[l] * texel_bytes(cfg)) * s);
                 D.w = sc.w; D.h = sc.h;
                 D.fx = (float)sc.fx; D.fy = (float)sc.fy; D.cx = (float)sc.cx; D.cy = (float)sc.cy; D.xi = (float)sc.xi;
                 D.wm1 = (float)(sc.w - 1); D.hm1 = (float)(sc.h - 1);
@@ -563,7 +577,8 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             // level images
             PrepDev Pd;
             std::memset(&Pd, 0, sizeof Pd);
-            Pd.ref_full = fr.ref; Pd.ref_pitch = fr.ref_pitch;
+            Pd.ref_full = (const uint8_t *)fr.ref; Pd.ref_pitch = fr.ref_pitch;
+            Pd.img = cfg.image_format;
             Pd.ref_w = C.ref.width; Pd.ref_h = C.ref.height;
             Pd.ref_level = ds == 2 ? (uint8_t *)(slot + ctx->s_ref[l]) : nullptr;
             Pd.downsample = ds; Pd.n_src = C.n_src;
@@ -680,7 +695,7 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
             const JobDev &J = (*host_jobs)[j];
             const int ntile = J.tiles_x * J.tiles_y;
             if (ntile == 0) continue;
-            const KernelEntry *e = find_kernel(J.window, J.rows, J.waves, J.n_src, store, soft, 0);
+            const KernelEntry *e = find_kernel(J.window, J.rows, J.waves, J.n_src, store, soft, 0, cfg.image_format);
             if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no kernel for this window/tile/sources/storage");
             JobDev *jp = dj + j;
             void *a[] = {&jp};
@@ -699,7 +714,7 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
             if (J.rows != ctx->tile_rows[0] || J.waves != ctx->tile_waves[0])
                 return fail(ctx, PSWEEP_EUNSUPPORTED, "persistent launch needs one tile shape");
         }
-        const KernelEntry *e = find_kernel(0, ctx->tile_rows[0], ctx->tile_waves[0], n_src, store, 0, 1);
+        const KernelEntry *e = find_kernel(0, ctx->tile_rows[0], ctx->tile_waves[0], n_src, store, 0, 1, 0);
         if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no persistent kernel for this tile/sources/storage");
         int *counter = (int *)(ctx->ws + ctx->off_counter[which]);
         {
@@ -887,7 +902,7 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
         PSW_HIP(hipLaunchKernel(zk, dim3(1), dim3(256), a, 0, stream), "zero");
     }
     const int win = ctx->cfg.level[0].window;
-    const void *bk = psw_backward_kernel(win, C.n_src);
+    const void *bk = psw_backward_kernel(win, C.n_src, ctx->cfg.image_format);
     if (!bk) return fail(ctx, PSWEEP_EUNSUPPORTED, "no backward kernel for this window / source count");
     const size_t lds = psw_backward_lds(win, C.n_src);
     if (lds > 65536) PSW_HIP(hipFuncSetAttribute(bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds limit");

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sweep_common.h"
 
 namespace psw {
@@ -32,7 +34,7 @@ __global__ void zero_kernel(float *p, int64_t n) {
         p[i] = 0.0f;
 }
 
-template <int WIN, int S>
+template <int WIN, int S, int IMG>
 struct Backward {
     static constexpr int NW = 4, R = 8;
     static constexpr int HW = WIN / 2;
@@ -73,29 +75,41 @@ struct Backward {
             yw[i] = ((float)v - J.cy) * J.inv_fy;
             const float t = ray_tau(x, yw[i], xi, nullptr);
             tf[i] = t > 0.0f ? t : __builtin_nanf("");
-            aw[i] = (sc < W && v < H) ? (float)gptr(J.ref)[(int64_t)v * J.ref_pitch + sc] - 128.0f : 0.0f;
+            aw[i] = (sc < W && v < H) ? Texel<IMG>::ref(J.ref, (int64_t)v * J.ref_pitch + sc) - 128.0f : 0.0f;
         }
         // rows this wave runs down (forward recompute of the window sums)
         float av[VR];
 #pragma unroll
         for (int m = 0; m < VR; ++m) {
             const int v = sr0 + wave * R + m;
-            av[m] = (sc < W && v < H) ? (float)gptr(J.ref)[(int64_t)v * J.ref_pitch + sc] - 128.0f : 0.0f;
+            av[m] = (sc < W && v < H) ? Texel<IMG>::ref(J.ref, (int64_t)v * J.ref_pitch + sc) - 128.0f : 0.0f;
         }
         float mean_a[R], isd_a[R], gp[R], rh[R], ls[R];
         uint32_t ref_ok = 0;
         {
+            // reference window sums: exact integers for 8-bit images, FP64 for float images
+            using Acc = typename std::conditional<IMG == 1, double, int>::type;
             const float N = (float)(WIN * WIN);
-            int va = 0, vaa = 0;
+            Acc va = 0, vaa = 0;
 #pragma unroll
             for (int m = 0; m < VR; ++m) {
-                const int a = (int)av[m];
-                va += a; vaa += a * a;
-                if (m >= WIN) { const int ao = (int)av[m - WIN]; va -= ao; vaa -= ao * ao; }
+                const Acc a = (Acc)av[m];
+                va += a;
+                if constexpr (IMG == 1) vaa = fma(a, a, vaa); else vaa += a * a;
+                if (m >= WIN) {
+                    const Acc ao = (Acc)av[m - WIN];
+                    va -= ao;
+                    if constexpr (IMG == 1) vaa = fma(-ao, ao, vaa); else vaa -= ao * ao;
+                }
                 if (m >= WIN - 1) {
                     const int i = m - (WIN - 1);
-                    const int sa = wsum_i<WIN>(va, sh), saa = wsum_i<WIN>(vaa, sh);
-                    const float var_a = (float)(WIN * WIN * saa - sa * sa) / N;
+                    Acc sa, saa;
+                    if constexpr (IMG == 1) { sa = wsum_d<WIN>(va, sh); saa = wsum_d<WIN>(vaa, sh); }
+                    else { sa = wsum_i<WIN>(va, sh); saa = wsum_i<WIN>(vaa, sh); }
+                    float var_a;
+                    // the same expressions as the forward sweep, so the costs agree bit for bit
+                    if constexpr (IMG == 1) var_a = (float)fma(-sa / (double)(WIN * WIN), sa, saa);
+                    else var_a = (float)(WIN * WIN * saa - sa * sa) / N;
                     const int orow = or0 + i;
                     const bool p = lane >= HW && lane < kWave - HW && sc <= W - 1 - HW && orow <= H - 1 - HW;
                     float g = 0.f, r = 0.f, l = -__builtin_huge_valf();
@@ -106,7 +120,8 @@ struct Backward {
                     const bool ok = p && var_a > J.var_floor_n && g != 0.0f && l > -__builtin_huge_valf() &&
                                     !__builtin_isnan(r);
                     ref_ok |= (ok ? 1u : 0u) << i;
-                    mean_a[i] = (float)sa / N;
+                    if constexpr (IMG == 1) mean_a[i] = (float)(sa / (double)(WIN * WIN));
+                    else mean_a[i] = (float)sa / N;
                     isd_a[i] = ok ? __builtin_amdgcn_rsqf(var_a) : 0.0f;
                     gp[i] = g; rh[i] = r; ls[i] = l;
                 }
@@ -128,7 +143,7 @@ struct Backward {
                 const float h1x = hm[0], h1y = hm[1], h1z = hm[2], h2x = hm[3], h2y = hm[4], h2z = hm[5];
                 const float h3x = hm[6], h3y = hm[7], h3z = hm[8];
                 const SrcDev &sd = J.src[s];
-                const uint32_t row_bytes = (uint32_t)sd.w * 4u;
+                const uint32_t row_bytes = (uint32_t)sd.w * Texel<IMG>::bytes;
                 const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                     (void *)sd.tex, (short)0, (int)(row_bytes * (uint32_t)sd.h), 0x00020000);
                 const float px = h1x * x, py = h1y * x, pz = h1z * x;
@@ -145,12 +160,10 @@ struct Backward {
                     const float u = fmaf(X * inv, sd.fx, sd.cx);
                     const float v = fmaf(Y * inv, sd.fy, sd.cy);
                     const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= sd.wm1) & (v >= 0.0f) & (v <= sd.hm1);
-                    const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + ((uint32_t)(int)u << 2);
+                    const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                     const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
-                    const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
-                    const float p00 = (float)(q & 0xffu), p10 = (float)((q >> 8) & 0xffu);
-                    const float p01 = (float)((q >> 16) & 0xffu), p11 = (float)(q >> 24);
-                    const float top = fmaf(al, p10 - p00, p00), bot = fmaf(al, p11 - p01, p01);
+                    const auto q = Texel<IMG>::load(rs, off);
+                    const float top = fmaf(al, q.p10 - q.p00, q.p00), bot = fmaf(al, q.p11 - q.p01, q.p01);
                     tile[((size_t)s * T + j) * kWave + lane] = ok ? fmaf(be, bot - top, top - 128.0f) : -0.0f;
                 }
             }
@@ -237,7 +250,7 @@ struct Backward {
                 const float h1x = hm[0], h1y = hm[1], h1z = hm[2], h2x = hm[3], h2y = hm[4], h2z = hm[5];
                 const float h3x = hm[6], h3y = hm[7], h3z = hm[8];
                 const SrcDev &sd = J.src[s];
-                const uint32_t row_bytes = (uint32_t)sd.w * 4u;
+                const uint32_t row_bytes = (uint32_t)sd.w * Texel<IMG>::bytes;
                 const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                     (void *)sd.tex, (short)0, (int)(row_bytes * (uint32_t)sd.h), 0x00020000);
                 const float px = h1x * x, py = h1y * x, pz = h1z * x;
@@ -273,10 +286,8 @@ struct Backward {
                     const int i1 = i0 + 1 < sd.w ? i0 + 1 : sd.w - 1;
                     const int j1 = j0 + 1 < sd.h ? j0 + 1 : sd.h - 1;
                     const float al = u - (float)i0, be = v - (float)j0;
-                    const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(
-                        rs, (int)(__umul24((uint32_t)j0, row_bytes) + ((uint32_t)i0 << 2)), 0, 0);
-                    const float p00 = (float)(q & 0xffu), p10 = (float)((q >> 8) & 0xffu);
-                    const float p01 = (float)((q >> 16) & 0xffu), p11 = (float)(q >> 24);
+                    const auto q = Texel<IMG>::load(rs, __umul24((uint32_t)j0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes);
+                    const float p00 = q.p00, p10 = q.p10, p01 = q.p01, p11 = q.p11;
                     float *gi = gimg;
                     atomicAdd(gi + (int64_t)j0 * sd.w + i0, gb * (1.0f - al) * (1.0f - be));
                     atomicAdd(gi + (int64_t)j0 * sd.w + i1, gb * al * (1.0f - be));
@@ -322,14 +333,14 @@ struct Backward {
     }
 };
 
-template <int WIN, int S>
+template <int WIN, int S, int IMG>
 __global__ __launch_bounds__(256) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
                                                         const float *__restrict__ rho, const float *__restrict__ lse,
                                                         int64_t spitch, float *g0, float *g1, float *g2, float *g3,
                                                         double *gpose) {
     extern __shared__ char smem[];
     float *gs[4] = {g0, g1, g2, g3};
-    Backward<WIN, S>::run(job, gin, rho, lse, spitch, gs, gpose, smem);
+    Backward<WIN, S, IMG>::run(job, gin, rho, lse, spitch, gs, gpose, smem);
 }
 
 }  // namespace psw
@@ -337,14 +348,14 @@ __global__ __launch_bounds__(256) void backward_kernel(const JobDev *__restrict_
 extern "C" {
 const void *psw_zero_kernel() { return (const void *)&psw::zero_kernel; }
 
-const void *psw_backward_kernel(int win, int n_src) {
-#define PSW_B(W)                                                            \
-    if (win == W) {                                                         \
-        if (n_src == 1) return (const void *)&psw::backward_kernel<W, 1>; \
-        if (n_src == 2) return (const void *)&psw::backward_kernel<W, 2>; \
-        if (n_src == 3) return (const void *)&psw::backward_kernel<W, 3>; \
+const void *psw_backward_kernel(int win, int n_src, int img) {
+#define PSW_B(W, I)                                                                      \
+    if (win == W && img == I) {                                                          \
+        if (n_src == 1) return (const void *)&psw::backward_kernel<W, 1, I>;            \
+        if (n_src == 2) return (const void *)&psw::backward_kernel<W, 2, I>;            \
+        if (n_src == 3) return (const void *)&psw::backward_kernel<W, 3, I>;            \
     }
-    PSW_B(5) PSW_B(7) PSW_B(9)
+    PSW_B(5, 0) PSW_B(7, 0) PSW_B(9, 0) PSW_B(5, 1) PSW_B(7, 1) PSW_B(9, 1)
 #undef PSW_B
     return nullptr;
 }
@@ -352,9 +363,9 @@ const void *psw_backward_kernel(int win, int n_src) {
 size_t psw_backward_lds(int win, int n_src) {
 #define PSW_L(W)                                                       \
     if (win == W) {                                                    \
-        if (n_src == 1) return psw::Backward<W, 1>::lds_bytes();       \
-        if (n_src == 2) return psw::Backward<W, 2>::lds_bytes();       \
-        if (n_src == 3) return psw::Backward<W, 3>::lds_bytes();       \
+        if (n_src == 1) return psw::Backward<W, 1, 0>::lds_bytes();    \
+        if (n_src == 2) return psw::Backward<W, 2, 0>::lds_bytes();    \
+        if (n_src == 3) return psw::Backward<W, 3, 0>::lds_bytes();    \
     }
     PSW_L(5) PSW_L(7) PSW_L(9)
 #undef PSW_L

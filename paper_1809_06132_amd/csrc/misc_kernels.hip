@@ -65,8 +65,20 @@ __global__ void prep_kernel(const PrepDev *__restrict__ preps) {
     const int s = which - 1;
     if (s >= P.n_src) return;
     const int lw = P.src_w[s] / ds, lh = P.src_h[s] / ds;
-    const uint8_t *img = P.src_full[s];
     const int64_t pitch = P.src_pitch[s];
+    if (P.img == 1) {
+        // float images (full resolution only): four floats per texel
+        const float *img = static_cast<const float *>(P.src_full[s]);
+        float4 *tex = reinterpret_cast<float4 *>(P.tex[s]);
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lw * lh; e += gridDim.x * blockDim.x) {
+            const int x = e % lw, y = e / lw;
+            const int x1 = min(x + 1, lw - 1), y1 = min(y + 1, lh - 1);
+            tex[e] = make_float4(img[(int64_t)y * pitch + x], img[(int64_t)y * pitch + x1],
+                                 img[(int64_t)y1 * pitch + x], img[(int64_t)y1 * pitch + x1]);
+        }
+        return;
+    }
+    const uint8_t *img = static_cast<const uint8_t *>(P.src_full[s]);
     uint32_t *tex = P.tex[s];
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lw * lh; e += gridDim.x * blockDim.x) {
         const int x = e % lw, y = e / lw;

@@ -13,7 +13,7 @@ constexpr int kWave = 64;
 
 // One source camera of one level, as the sweep kernel reads it.
 struct SrcDev {
-    const uint32_t *tex;   // 2x2-quad packed texels, row pitch = w (elements)
+    const uint32_t *tex;   // 2x2-quad packed texels (u8 x 4 or float x 4), row pitch = w texels
     int32_t w, h;
     float fx, fy, cx, cy, xi;
     float wm1, hm1;        // w - 1, h - 1 (inclusive sample bounds)
@@ -23,7 +23,8 @@ struct SrcDev {
 // Everything the kernels need for one (frame, level).  Lives in device
 // memory (the workspace); read through the scalar cache.
 struct JobDev {
-    // reference view of the level (downsampled copy or a view into the frame)
+    // reference view of the level (downsampled copy or a view into the
+    // frame); uint8_t, or float for the float-image kernels; pitch in elements
     const uint8_t *ref;
     int64_t ref_pitch;
     int32_t w, h;
@@ -92,10 +93,11 @@ struct PrepDev {
     int32_t ref_w, ref_h;          // full-resolution reference size
     uint8_t *ref_level;            // downsampled reference (downsample == 2), else null
     int32_t downsample, n_src;
-    const uint8_t *src_full[kMaxSrc];
-    int64_t src_pitch[kMaxSrc];
+    const void *src_full[kMaxSrc]; // uint8_t or float images (img)
+    int64_t src_pitch[kMaxSrc];    // elements
     int32_t src_w[kMaxSrc], src_h[kMaxSrc];   // full-resolution sizes
-    uint32_t *tex[kMaxSrc];                   // level-size quad textures
+    uint32_t *tex[kMaxSrc];        // level-size quad textures: one u32 (4 x u8) or 4 floats per texel
+    int32_t img, pad;
 };
 
 // Full-resolution merge of a frame's levels.
@@ -159,7 +161,8 @@ struct FilterDev {
 struct KernelEntry {
     int win, rows, waves, n_src, store, soft, persistent;
     const void *fn;
-    size_t lds;   // dynamic LDS bytes
+    size_t lds;     // dynamic LDS bytes
+    int img = 0;    // frame pixel type: 0 uint8, 1 float
 };
 
 }  // namespace psw
@@ -170,3 +173,4 @@ extern "C" int psw_kernels_extra(const psw::KernelEntry **out);
 extern "C" int psw_kernels_small(const psw::KernelEntry **out);
 extern "C" int psw_kernels_grid8(const psw::KernelEntry **out);
 extern "C" int psw_kernels_persistent(const psw::KernelEntry **out);
+extern "C" int psw_kernels_f32img(const psw::KernelEntry **out);

@@ -121,6 +121,45 @@ template <int WIN>
 __device__ __forceinline__ int wsum_i(int v, const Shifts &sh) {
     return window_sum<WIN>(v, sh, shr1_i, lane_from_i);
 }
+// doubles move between lanes as two 32-bit halves
+__device__ __forceinline__ double shr1_d(double v) {
+    return __hiloint2double(shr1_i(__double2hiint(v)), shr1_i(__double2loint(v)));
+}
+__device__ __forceinline__ double lane_from_d(double v, int addr) {
+    return __hiloint2double(lane_from_i(__double2hiint(v), addr), lane_from_i(__double2loint(v), addr));
+}
+template <int WIN>
+__device__ __forceinline__ double wsum_d(double v, const Shifts &sh) {
+    return window_sum<WIN>(v, sh, shr1_d, lane_from_d);
+}
+
+// One bilinear sample of a quad-packed source texture at texel (iu, iv) with
+// weights (al, be), centred (minus 128).  IMG 0: a u32 holds the 2x2 grey
+// levels; IMG 1: four floats.  Reads outside the buffer return 0.
+template <int IMG>
+struct Texel;
+template <>
+struct Texel<0> {
+    static constexpr uint32_t bytes = 4;
+    struct Quad { float p00, p10, p01, p11; };
+    __device__ static Quad load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+        const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+        return {(float)(q & 0xffu), (float)((q >> 8) & 0xffu), (float)((q >> 16) & 0xffu), (float)(q >> 24)};
+    }
+    __device__ static float ref(const uint8_t *p, int64_t i) { return (float)gptr(p)[i]; }
+};
+template <>
+struct Texel<1> {
+    static constexpr uint32_t bytes = 16;
+    struct Quad { float p00, p10, p01, p11; };
+    __device__ static Quad load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        return {__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3])};
+    }
+    __device__ static float ref(const uint8_t *p, int64_t i) {
+        return gptr(reinterpret_cast<const float *>(p))[i];
+    }
+};
 
 // lanes whose window [l-h, l+h] contains a lane with bit set in m
 template <int WIN>
@@ -214,7 +253,7 @@ __device__ __forceinline__ void finish_soft(const JobDev &J, int orow, int col, 
 // ---------------------------------------------------------------------------
 // the sweep of one tile
 // ---------------------------------------------------------------------------
-template <int WIN, int R, int NW, int S, int STORE, bool SOFT>
+template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0>
 struct Tile {
     static constexpr int HW = WIN / 2;
     static constexpr int TXO = kWave - 2 * HW;       // output columns per tile
@@ -255,14 +294,38 @@ struct Tile {
 #pragma unroll
             for (int m = 0; m < VR; ++m) {
                 const int v = sr0 + wave * R + m;
-                av[m] = (col_in && v < H) ? (float)gptr(J.ref)[(int64_t)v * J.ref_pitch + sc] - 128.0f : 0.0f;
+                av[m] = (col_in && v < H) ? Texel<IMG>::ref(J.ref, (int64_t)v * J.ref_pitch + sc) - 128.0f : 0.0f;
             }
         }
-        // reference window statistics of the wave's output pixels (exact in
-        // integers: |a'| <= 128, window sums of a'^2 < 2^24)
         float mean_a[R], isd_a[R];
         uint32_t pos_ok = 0, ref_ok = 0;
-        {
+        if constexpr (IMG == 1) {
+            // float images: window sums in FP64 (products of floats are exact)
+            const double N = (double)(WIN * WIN);
+            double va = 0.0, vaa = 0.0;
+#pragma unroll
+            for (int m = 0; m < VR; ++m) {
+                const double a = av[m];
+                va += a; vaa = fma(a, a, vaa);
+                if (m >= WIN) {
+                    const double ao = av[m - WIN];
+                    va -= ao; vaa = fma(-ao, ao, vaa);
+                }
+                if (m >= WIN - 1) {
+                    const int i = m - (WIN - 1);
+                    const double sa = wsum_d<WIN>(va, sh), saa = wsum_d<WIN>(vaa, sh);
+                    const float var_a = (float)fma(-sa / N, sa, saa);   // sum of squared deviations
+                    const int orow = or0 + i;
+                    const bool p = lane >= HW && lane < kWave - HW && sc <= W - 1 - HW && orow <= H - 1 - HW;
+                    const bool r = p && var_a > J.var_floor_n;
+                    pos_ok |= (p ? 1u : 0u) << i;
+                    ref_ok |= (r ? 1u : 0u) << i;
+                    mean_a[i] = (float)(sa / N);
+                    isd_a[i] = r ? __builtin_amdgcn_rsqf(var_a) : 0.0f;
+                }
+            }
+        } else {
+            // 8-bit images: exact in integers (|a'| <= 128, window sums of a'^2 < 2^24)
             const float N = (float)(WIN * WIN);
             int va = 0, vaa = 0;
 #pragma unroll
@@ -354,7 +417,7 @@ struct Tile {
                     const float sxi = J.src[s].xi, sfx = J.src[s].fx, sfy = J.src[s].fy;
                     const float scx = J.src[s].cx, scy = J.src[s].cy;
                     const float wm1 = J.src[s].wm1, hm1 = J.src[s].hm1;
-                    const uint32_t row_bytes = (uint32_t)J.src[s].w * 4u;
+                    const uint32_t row_bytes = (uint32_t)J.src[s].w * Texel<IMG>::bytes;
                     // buffer reads outside the texture return 0, so even the
                     // address of an invalid sample cannot fault
                     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -374,13 +437,11 @@ struct Tile {
                         const float u = fmaf(X * inv, sfx, scx);
                         const float v = fmaf(Y * inv, sfy, scy);
                         const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= wm1) & (v >= 0.0f) & (v <= hm1);
-                        const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + ((uint32_t)(int)u << 2);
+                        const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                         const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
-                        const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
-                        const float p00 = (float)(q & 0xffu), p10 = (float)((q >> 8) & 0xffu);
-                        const float p01 = (float)((q >> 16) & 0xffu), p11 = (float)(q >> 24);
-                        const float top = fmaf(al, p10 - p00, p00);
-                        const float bot = fmaf(al, p11 - p01, p01);
+                        const auto q = Texel<IMG>::load(rs, off);
+                        const float top = fmaf(al, q.p10 - q.p00, q.p00);
+                        const float bot = fmaf(al, q.p11 - q.p01, q.p01);
                         const float b = fmaf(be, bot - top, top - 128.0f);
                         dst[(size_t)j * kWave] = St::put(ok ? b : -0.0f);
                     }
@@ -497,7 +558,7 @@ struct Tile {
 // chunk after another.  Every XCD so holds an equal share of the image's
 // upper and lower parts (ground-plane chunks cost little above the horizon),
 // and its resident workgroups sweep the same planes over nearby tiles.
-template <int WIN, int R, int NW, int S, int STORE, bool SOFT>
+template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0>
 __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__restrict__ job) {
     extern __shared__ char smem[];
     const int nch = job->nch_f + job->nch_g;
@@ -510,7 +571,7 @@ __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__r
     const int chunk = i / per_chunk;
     const int r = i - chunk * per_chunk;
     const int tile_y = x + 8 * (r / tx);
-    Tile<WIN, R, NW, S, STORE, SOFT>::run(job, r % tx, tile_y, chunk, smem);
+    Tile<WIN, R, NW, S, STORE, SOFT, IMG>::run(job, r % tx, tile_y, chunk, smem);
 }
 
 // One persistent launch for every (frame, level, tile) of a run: workgroups

@@ -18,6 +18,7 @@ OK, EINVAL, ESTATE, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 STORAGE_F32, STORAGE_F16, STORAGE_BF16 = 0, 1, 2
 MODE_WTA, MODE_SOFT = 0, 1
 LAUNCH_GRID, LAUNCH_PERSISTENT = 0, 1
+IMAGE_U8, IMAGE_F32 = 0, 1
 
 _d, _i32, _i64, _p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
 
@@ -53,7 +54,7 @@ class psweep_config(ctypes.Structure):
     _fields_ = [("n_levels", _i32), ("level", psweep_level * MAX_LEVELS), ("ground_n", _d * 3), ("ground_d", _d),
                 ("best_k", _i32), ("var_floor", _d), ("storage", _i32), ("mode", _i32), ("temperature", _d),
                 ("launch", _i32), ("max_width", _i32), ("max_height", _i32), ("max_sources", _i32),
-                ("max_frames", _i32), ("max_camera_sets", _i32)]
+                ("max_frames", _i32), ("max_camera_sets", _i32), ("image_format", _i32)]
 
 
 class psweep_frame(ctypes.Structure):

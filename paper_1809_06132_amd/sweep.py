@@ -15,11 +15,12 @@ import torch
 from . import psweep as P
 
 _STORAGE = {"f32": P.STORAGE_F32, "f16": P.STORAGE_F16, "bf16": P.STORAGE_BF16}
+_IMAGE = {"u8": (P.IMAGE_U8, torch.uint8), "f32": (P.IMAGE_F32, torch.float32)}
 _LAUNCH = {"grid": P.LAUNCH_GRID, "persistent": P.LAUNCH_PERSISTENT}
 
 
 def make_config(settings, max_width, max_height, max_sources, max_frames=1, max_camera_sets=1,
-                storage="f32", launch="grid") -> P.psweep_config:
+                storage="f32", launch="grid", image_format="u8") -> P.psweep_config:
     c = P.psweep_config()
     c.n_levels = len(settings.levels)
     for i, lv in enumerate(settings.levels):
@@ -38,6 +39,7 @@ def make_config(settings, max_width, max_height, max_sources, max_frames=1, max_
     c.launch = _LAUNCH[launch]
     c.max_width, c.max_height = int(max_width), int(max_height)
     c.max_sources, c.max_frames, c.max_camera_sets = int(max_sources), int(max_frames), int(max_camera_sets)
+    c.image_format = _IMAGE[image_format][0]
     return c
 
 
@@ -62,13 +64,14 @@ class PlaneSweep:
     """A context, its workspace and output allocation helpers."""
 
     def __init__(self, settings, max_width, max_height, max_sources, max_frames=1, max_camera_sets=1,
-                 storage="f32", launch="grid", device="cuda:0"):
+                 storage="f32", launch="grid", device="cuda:0", image_format="u8"):
         if not torch.cuda.is_available():
             raise RuntimeError("PlaneSweep needs a GPU (the sweep has no CPU path)")
         self.settings = settings
         self.device = torch.device(device)
+        self.image_dtype = _IMAGE[image_format][1]
         self.cfg = make_config(settings, max_width, max_height, max_sources, max_frames, max_camera_sets,
-                               storage, launch)
+                               storage, launch, image_format)
         self.ctx = P.psweep_create(self.cfg)
         n = P.psweep_workspace_size(self.ctx)
         self.workspace = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
@@ -157,10 +160,13 @@ class PlaneSweep:
     def _frame(self, fr: dict) -> P.psweep_frame:
         f = P.psweep_frame()
         ref = fr["ref"]
-        assert ref.dtype == torch.uint8 and ref.is_cuda and ref.dim() == 2 and ref.stride(1) == 1
+        dt = self.image_dtype
+        if ref.dtype != dt or ref.device.type != "cuda" or ref.dim() != 2 or ref.stride(1) != 1:
+            raise ValueError(f"reference must be a 2-D row-major {dt} CUDA tensor")
         f.ref, f.ref_pitch = ref.data_ptr(), ref.stride(0)
         for s, img in enumerate(fr["srcs"]):
-            assert img.dtype == torch.uint8 and img.is_cuda and img.dim() == 2 and img.stride(1) == 1
+            if img.dtype != dt or img.device.type != "cuda" or img.dim() != 2 or img.stride(1) != 1:
+                raise ValueError(f"source {s} must be a 2-D row-major {dt} CUDA tensor")
             f.src[s], f.src_pitch[s] = img.data_ptr(), img.stride(0)
         f.camera_set = int(fr.get("camera_set", 0))
         return f
@@ -224,8 +230,10 @@ class PlaneSweep:
         return gs, gp
 
 
-def frame_to_device(frame, device="cuda:0"):
-    """Upload a scenegen-style frame (numpy uint8 images) to the GPU."""
-    return {"ref": torch.from_numpy(np.ascontiguousarray(frame.ref)).to(device),
-            "srcs": [torch.from_numpy(np.ascontiguousarray(s)).to(device) for s in frame.srcs],
-            "camera_set": 0}
+def frame_to_device(frame, device="cuda:0", dtype=None):
+    """Upload a scenegen-style frame (numpy images) to the GPU, converted to
+    `dtype` when given (torch.uint8 or torch.float32)."""
+    def up(a):
+        t = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return t if dtype is None else t.to(dtype)
+    return {"ref": up(frame.ref), "srcs": [up(s) for s in frame.srcs], "camera_set": 0}

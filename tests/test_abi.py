@@ -62,6 +62,10 @@ def _cfg(psweep, **kw):
     ({"mode": 1, "launch": 1}, -5),
     ({"launch": 1, "0.window": 5}, -5),
     ({"0.crop_w": 100, "0.crop_h": 100}, -5),
+    ({"image_format": 2}, -1),                                              # unknown pixel type
+    ({"image_format": 1, "0.downsample": 2}, -5),                           # float images: full resolution
+    ({"image_format": 1, "0.window": 9, "launch": 1}, -5),                  # float images: grid launch
+    ({"image_format": 1, "storage": 1}, -5),                                # float images: FP32 staging
 ])
 def test_create_rejects_bad_config(kw, status):
     psweep = _lib_or_skip()
