@@ -159,6 +159,116 @@ def bench_c5(args):
     print(json.dumps(line), flush=True)
 
 
+def _time_runs(ps, frames, outs, steps, warmup):
+    """Median, p10 and p90 of whole psweep_run calls, from HIP events on the
+    launch stream (torch's current stream)."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        ps.run(frames, outs)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ps.run(frames, outs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    p10, p50, p90 = (float(v) for v in np.percentile(ms, [10, 50, 90]))
+    return p50, [p10, p50, p90]
+
+
+def bench_levels(args):
+    """Two-level maps: C3 (1024x768, 3 sources; low 512x384 with 96 planes at
+    7x7, full-resolution 512x384 centre crop with 64 planes at 9x9) in every
+    staging precision, and the paper's shape (1024x544; 64 + 30 planes on the
+    512x272 level at 7x7 and on the 572x332 full-resolution crop at 9x9) with
+    5 cameras (4 sources) and with 3 (the two nearest sources)."""
+    import torch
+
+    import scenegen
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+
+    rows = []
+    if args.workload == "C3":
+        wl = scenegen.workload("C3")
+        cases = [("C3", wl.frames[0], wl.settings, list(range(3)), st) for st in ("f32", "f16", "bf16")]
+    else:
+        wl = scenegen.workload("paper")
+        cases = [("paper", wl.frames[0], wl.settings, list(range(4)), "f32"),
+                 ("paper", wl.frames[0], wl.settings, [0, 1], "f32")]
+    for name, fr, st, srcs, storage in cases:
+        W, H = fr.ref_cam.width, fr.ref_cam.height
+        ps = PlaneSweep(st, W, H, len(srcs), storage=storage)
+        ps.set_cameras(0, fr.ref_cam, [fr.src_cams[i] for i in srcs], [fr.poses[i] for i in srcs])
+        d = frame_to_device(fr)
+        d["srcs"] = [d["srcs"][i] for i in srcs]
+        out = ps.alloc_outputs()
+        pp = ps.plane_pixels([d])
+        med, pct = _time_runs(ps, [d], [out], args.steps, args.warmup)
+        ps.close()
+        rows.append({"workload": name, "cameras": len(srcs) + 1, "storage": storage, "ms_per_map": med,
+                     "ms_p10_p50_p90": pct, "maps_per_s": 1e3 / med, "plane_pixels_per_map": pp,
+                     "gpix_planes_per_s": pp / (med * 1e-3) / 1e9})
+    line = {"metric": METRIC, "workload": args.workload, "results": rows}
+    if args.workload == "paper":
+        line["context"] = ("the paper's multi-scale depth stage: 36 ms per frame with 5 cameras on a GTX 1080; "
+                           "3 cameras about 17% less")
+        line["three_vs_five_cameras_time_ratio"] = rows[1]["ms_per_map"] / rows[0]["ms_per_map"]
+    print(json.dumps(line), flush=True)
+
+
+def bench_c4(args):
+    """C4: soft-argmin forward and backward (640x480, 2 sources, 64 fronto
+    planes, 7x7, T = 0.1) on the GPU, and the FP64 oracle's backward on the
+    64x48 crop the gradient checks use (timed on the host cores)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import scenegen
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+
+    wl = scenegen.workload("C4")
+    fr, st = wl.frames[0], wl.settings
+    W, H, S = fr.ref_cam.width, fr.ref_cam.height, len(fr.srcs)
+    ps = PlaneSweep(st, W, H, S)
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    d = frame_to_device(fr)
+    out = ps.alloc_outputs()
+    pp = ps.plane_pixels([d])
+    fwd, fwd_pct = _time_runs(ps, [d], [out], args.steps, args.warmup)
+    g = torch.randn((H, W), device="cuda", generator=torch.Generator(device="cuda").manual_seed(0))
+    shapes = [s.shape for s in fr.srcs]
+    for _ in range(args.warmup):
+        ps.soft_backward(g, shapes)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ps.soft_backward(g, shapes)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ps.close()
+    bwd = float(np.median(ms))
+    line = {"metric": METRIC, "workload": "C4", "plane_pixels": pp, "forward_ms": fwd,
+            "forward_ms_p10_p50_p90": fwd_pct, "forward_gpix_planes_per_s": pp / (fwd * 1e-3) / 1e9,
+            "backward_ms": bwd, "backward_ms_p10_p50_p90": [float(v) for v in np.percentile(ms, [10, 50, 90])]}
+    if not args.no_cpu:
+        rect = (288, 216, 64, 48)
+        rng = np.random.default_rng(0)
+        gg = rng.normal(size=(rect[3], rect[2]))
+        t0 = time.perf_counter()
+        oracle.soft_backward(st.levels[0], st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, rect, gg)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline_backward"] = {"seconds": dt, "cores": oracle.threads(), "kind": "oracle",
+                                         "sample": "FP64 backward on the 64x48 crop at (288, 216), all 64 planes"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,18 +276,26 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--workload", default="C2", choices=["C2", "C5"],
-                    help="C2 (default): the benchmark line; C5: batched vs plain comparison")
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5", "paper"],
+                    help="C2 (default): the benchmark line; C3: two-level maps per staging precision; "
+                         "C4: soft forward and backward; C5: batched vs plain; paper: the paper's shape "
+                         "with 5 and 3 cameras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build sweeps on one "
-              "device; see the sharding notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the sweep runs on one "
+              "device (frames, or plane ranges, would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "C5":
         bench_c5(args)
+        return
+    if args.workload in ("C3", "paper"):
+        bench_levels(args)
+        return
+    if args.workload == "C4":
+        bench_c4(args)
         return
 
     import torch

@@ -173,3 +173,26 @@ def test_plane_chunks_bitwise_equal():
     for n in (2, 3, 5, 8):
         for k in maps[1]:
             assert np.array_equal(maps[1][k], maps[n][k], equal_nan=True), (n, k)
+
+
+def test_paper_shape_levels_sampled():
+    """The paper's shape (Sec. III-A): 1024x544 with 4 sources, 64 fronto +
+    30 ground planes on the 512x272 level (7x7) and on the 572x332
+    full-resolution crop (9x9).  Each level map is checked against the
+    oracle on seeded sampled pixels."""
+    wl = scenegen.workload("paper")
+    fr, st = wl.frames[0], wl.settings
+    g = _run(st, fr, level_maps=True)
+    rng = np.random.default_rng(77)
+    for l, lv in enumerate(st.levels):
+        rc, rimg, scs, simgs = oracle.level_inputs(fr, lv)
+        n = 400
+        pix = np.stack([rng.integers(0, rc.width, n), rng.integers(0, rc.height, n)], 1).astype(np.int32)
+        ref = oracle.sweep_level(lv, st, rc, rimg, scs, simgs, fr.poses, pixels=pix, volume=True)
+        gl = g["levels"][l]
+        gs = {k: gl[k][pix[:, 1], pix[:, 0]] for k in ("index", "cost1")}
+        s = wta_stats({"index": gs["index"], "depth": np.where(gs["index"] >= 0, 1.0, np.nan), "cost1": gs["cost1"]},
+                      {"index": ref["index"], "depth": np.where(ref["index"] >= 0, 1.0, np.nan),
+                       "cost1": ref["cost1"]}, ref["volume"])
+        print("paper level", l, s)
+        assert_wta_parity(s)
