@@ -232,6 +232,19 @@ psweep_status psweep_filter(psweep_ctx *ctx, int32_t camera_set, const psweep_ma
                             const psweep_filter_params *params, float *out_depth, uint8_t *out_code,
                             int64_t out_pitch, void *hip_stream);
 
+/* Remove potentially moving objects from a depth map (Sec. III overview and
+ * Sec. IV-B: the detector's bounding boxes are masked out of the reference
+ * depth map before fusion).  boxes: host array of n_boxes x 4 int32 (x0, y0,
+ * x1, y1), the half-open pixel rectangle [x0, x1) x [y0, y1) of the camera
+ * set's full-resolution reference image; parts outside the image are
+ * ignored, empty boxes are allowed.  Every pixel inside a box gets depth NaN
+ * and, if code is not NULL, code 4.  pitch in elements, 0 = the image width.
+ * Asynchronous on hip_stream (the box list is copied before the call
+ * returns).  EINVAL for NULL depth, NULL boxes with n_boxes > 0, or n_boxes <
+ * 0; ESTATE for an undefined camera set. */
+psweep_status psweep_mask_boxes(psweep_ctx *ctx, int32_t camera_set, float *depth, uint8_t *code, int64_t pitch,
+                                int32_t n_boxes, const int32_t *boxes, void *hip_stream);
+
 /* Plane chunks per tile for one level: each tile's planes are cut into
  * n_chunks contiguous ranges swept by separate workgroups (more parallelism
  * on small images) and combined exactly afterwards; 0 = automatic (about ten

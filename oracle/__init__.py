@@ -407,3 +407,21 @@ def depth_filter(cam, ground_n, depth, cost1, cost2, alpha_upper=0.05, alpha_low
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().or_threads())
+
+
+# ----------------------------------------------------------------------------
+# dynamic-object masking (Sec. III overview, Sec. IV-B)
+# ----------------------------------------------------------------------------
+def mask_boxes(depth, boxes, code=None):
+    """Pixels inside any detected box [x0, x1) x [y0, y1) leave the depth map
+    (NaN; code 4).  Returns new arrays."""
+    d = np.array(depth, dtype=np.float64, copy=True)
+    c = None if code is None else np.array(code, copy=True)
+    h, w = d.shape
+    for x0, y0, x1, y1 in boxes:
+        for y in range(max(y0, 0), min(y1, h)):
+            for x in range(max(x0, 0), min(x1, w)):
+                d[y, x] = np.nan
+                if c is not None:
+                    c[y, x] = 4
+    return d, c

@@ -1,8 +1,10 @@
-"""Tile-shape autotuner of the sweep kernel.
+"""Autotuner of the sweep launch: tile shape and plane chunks per level.
 
-For every level of a workload it times each compiled tile shape (rows per
-wave x waves per workgroup) with the library's own HIP-event kernel timing
-and keeps the fastest, then remembers the choice in a JSON cache keyed by the
+For every level of a workload it first times each compiled tile shape (rows
+per wave x waves per workgroup) with the library's own HIP-event timing of
+the sweep kernel and keeps the fastest; then, level by level, it times whole
+runs (sweep plus the combine of plane chunks) for each plane-chunk count and
+keeps the fastest.  The choice is remembered in a JSON cache keyed by the
 device, the level shapes, the source count, the staging precision and the
 launch kind.  Deterministic: a cached choice is reused as is."""
 from __future__ import annotations
@@ -15,6 +17,7 @@ import torch
 from .sweep import PlaneSweep
 
 CANDIDATES = [(4, 4), (8, 4), (4, 8), (2, 8), (16, 4), (8, 2)]
+CHUNK_CANDIDATES = [0, 1, 2, 4, 6, 8]     # 0: the library's automatic count
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "psweep_tiles.json")
 
 
@@ -38,11 +41,33 @@ def _time(sweep, frames, outputs, reps):
     return best
 
 
+def _run_ms(sweep, frames, outputs, reps):
+    """Fastest whole run (every kernel of psweep_run), HIP events on the
+    launch stream."""
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sweep.run(frames, outputs)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def _apply(sweep, choice):
+    for l, (r, w) in enumerate(choice["tiles"]):
+        sweep.set_tile(l, r, w)
+    for l, c in enumerate(choice.get("chunks", [0] * len(choice["tiles"]))):
+        sweep.set_chunks(l, c)
+
+
 def tune(sweep: PlaneSweep, frames, outputs, reps: int = 5, cache_path: str | None = DEFAULT_CACHE,
-         candidates=CANDIDATES) -> dict:
+         candidates=CANDIDATES, chunk_candidates=CHUNK_CANDIDATES) -> dict:
     """Pick a tile shape per level (one shape for all levels with the
-    persistent launch).  Returns {"key": ..., "tiles": [[rows, waves], ...],
-    "ms": ...} and applies it to `sweep`."""
+    persistent launch), then a plane-chunk count per level.  Returns {"key":
+    ..., "tiles": [[rows, waves], ...], "chunks": [...], "ms": ...} and
+    applies it to `sweep`."""
     key = _key(sweep, frames)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -54,8 +79,7 @@ def tune(sweep: PlaneSweep, frames, outputs, reps: int = 5, cache_path: str | No
     nl = len(sweep.settings.levels)
     if key in cache:
         choice = cache[key]
-        for l, (r, w) in enumerate(choice["tiles"]):
-            sweep.set_tile(l, r, w)
+        _apply(sweep, choice)
         return choice
     persistent = sweep.cfg.launch == 1
     results = {}
@@ -90,7 +114,21 @@ def tune(sweep: PlaneSweep, frames, outputs, reps: int = 5, cache_path: str | No
             ms += per_level[best][l]
     for l, (r, w) in enumerate(tiles):
         sweep.set_tile(l, r, w)
-    choice = {"key": key, "tiles": tiles, "ms": ms, "candidates": {f"{r}x{w}": v for (r, w), v in results.items()}}
+    # plane chunks, level by level, on whole-run time (the combine of chunks
+    # is a kernel of its own)
+    chunks, chunk_ms = [], {}
+    for l in range(nl):
+        best_c, best_t = 0, float("inf")
+        for c in chunk_candidates:
+            sweep.set_chunks(l, c)
+            t = _run_ms(sweep, frames, outputs, reps)
+            chunk_ms[f"level{l}:{c}"] = t
+            if t < best_t:
+                best_c, best_t = c, t
+        sweep.set_chunks(l, best_c)
+        chunks.append(best_c)
+    choice = {"key": key, "tiles": tiles, "chunks": chunks, "ms": ms, "run_ms": min(chunk_ms.values()),
+              "candidates": {f"{r}x{w}": v for (r, w), v in results.items()}, "chunk_candidates": chunk_ms}
     if cache_path:
         cache[key] = choice
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)

@@ -23,6 +23,7 @@ extern "C" const void *psw_reset_kernel();
 extern "C" const void *psw_merge_kernel();
 extern "C" const void *psw_chunk_merge_kernel();
 extern "C" const void *psw_filter_kernel();
+extern "C" const void *psw_mask_kernel();
 extern "C" const void *psw_backward_kernel(int win, int n_src, int img);
 extern "C" size_t psw_backward_lds(int win, int n_src);
 extern "C" const void *psw_zero_kernel();
@@ -954,6 +955,40 @@ psweep_status psweep_filter(psweep_ctx *ctx, int32_t camera_set, const psweep_ma
     PSW_HIP(hipLaunchKernel(psw_filter_kernel(), dim3((c.width + 15) / 16, (c.height + 15) / 16), dim3(16, 16), a, 0,
                             stream), "filter");
     return PSWEEP_OK;
+}
+
+psweep_status psweep_mask_boxes(psweep_ctx *ctx, int32_t camera_set, float *depth, uint8_t *code, int64_t pitch,
+                                int32_t n_boxes, const int32_t *boxes, void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (camera_set < 0 || camera_set >= (int)ctx->sets.size() || !ctx->sets[camera_set].defined)
+        return fail(ctx, PSWEEP_ESTATE, "undefined camera set");
+    if (!depth || n_boxes < 0 || (n_boxes > 0 && !boxes)) return fail(ctx, PSWEEP_EINVAL, "NULL depth or boxes");
+    const psweep_camera &c = ctx->sets[camera_set].ref;
+    if (pitch != 0 && pitch < c.width) return fail(ctx, PSWEEP_EINVAL, "pitch below width");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    MaskDev M;
+    std::memset(&M, 0, sizeof M);
+    M.depth = depth; M.code = code; M.pitch = pitch ? pitch : c.width;
+    M.w = c.width; M.h = c.height;
+    auto flush = [&]() -> psweep_status {
+        if (M.n == 0) return PSWEEP_OK;
+        void *a[] = {&M};
+        PSW_HIP(hipLaunchKernel(psw_mask_kernel(), dim3(64, M.n), dim3(256), a, 0, stream), "mask");
+        M.n = 0;
+        return PSWEEP_OK;
+    };
+    for (int b = 0; b < n_boxes; ++b) {
+        // clip to the image; boxes left empty are dropped
+        const int x0 = std::max(boxes[4 * b + 0], 0), y0 = std::max(boxes[4 * b + 1], 0);
+        const int x1 = std::min(boxes[4 * b + 2], c.width), y1 = std::min(boxes[4 * b + 3], c.height);
+        if (x1 <= x0 || y1 <= y0) continue;
+        M.box[M.n][0] = x0; M.box[M.n][1] = y0; M.box[M.n][2] = x1; M.box[M.n][3] = y1;
+        if (++M.n == kMaxMaskBoxes) {
+            const psweep_status st = flush();
+            if (st != PSWEEP_OK) return st;
+        }
+    }
+    return flush();
 }
 
 void psweep_destroy(psweep_ctx *ctx) {

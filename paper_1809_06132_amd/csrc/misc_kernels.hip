@@ -309,8 +309,25 @@ __global__ __launch_bounds__(256) void filter_kernel(const FilterDev F) {
 
 }  // namespace psw
 
+namespace psw {
+
+// blockIdx.y: box; the block's threads cover the box's pixels row by row
+__global__ void mask_kernel(MaskDev M) {
+    const int b = blockIdx.y;
+    const int x0 = M.box[b][0], y0 = M.box[b][1], x1 = M.box[b][2], y1 = M.box[b][3];
+    const int bw = x1 - x0, n = bw * (y1 - y0);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int64_t o = (int64_t)(y0 + e / bw) * M.pitch + x0 + e % bw;
+        M.depth[o] = __builtin_nanf("");
+        if (M.code) M.code[o] = 4;
+    }
+}
+
+}  // namespace psw
+
 extern "C" {
 const void *psw_filter_kernel() { return (const void *)&psw::filter_kernel; }
+const void *psw_mask_kernel() { return (const void *)&psw::mask_kernel; }
 const void *psw_chunk_merge_kernel() { return (const void *)&psw::chunk_merge_kernel; }
 const void *psw_setup_kernel() { return (const void *)&psw::setup_kernel; }
 const void *psw_prep_kernel() { return (const void *)&psw::prep_kernel; }

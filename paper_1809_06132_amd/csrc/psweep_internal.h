@@ -157,6 +157,16 @@ struct FilterDev {
     int64_t out_pitch;
 };
 
+// Box masking of a depth map: boxes passed by value, kMaxMaskBoxes per launch.
+constexpr int kMaxMaskBoxes = 64;
+struct MaskDev {
+    float *depth;
+    uint8_t *code;
+    int64_t pitch;
+    int32_t w, h, n, pad;
+    int32_t box[kMaxMaskBoxes][4];   // clipped x0, y0, x1, y1
+};
+
 // One compiled variant of the sweep kernel.
 struct KernelEntry {
     int win, rows, waves, n_src, store, soft, persistent;

@@ -26,7 +26,7 @@ _d, _i32, _i64, _p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_v
 EXPORTS = ["psweep_create", "psweep_workspace_size", "psweep_set_workspace", "psweep_set_cameras",
            "psweep_set_crop", "psweep_run", "psweep_soft_depth_backward", "psweep_set_tile",
            "psweep_graph_capture", "psweep_graph_launch", "psweep_set_timing", "psweep_sweep_kernel_ms",
-           "psweep_sweep_kernel_times", "psweep_set_chunks", "psweep_filter",
+           "psweep_sweep_kernel_times", "psweep_set_chunks", "psweep_filter", "psweep_mask_boxes",
            "psweep_plane_pixels", "psweep_destroy", "psweep_last_error", "psweep_version"]
 
 
@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
     L.psweep_set_tile.argtypes = [_p, _i32, _i32, _i32]
     L.psweep_set_chunks.argtypes = [_p, _i32, _i32]
     L.psweep_filter.argtypes = [_p, _i32, P(psweep_maps), P(psweep_filter_params), _p, _p, _i64, _p]
+    L.psweep_mask_boxes.argtypes = [_p, _i32, _p, _p, _i64, _i32, P(_i32), _p]
     L.psweep_graph_capture.argtypes = [_p, P(psweep_frame), _i32, P(psweep_output), _p]
     L.psweep_graph_launch.argtypes = [_p, _p]
     L.psweep_set_timing.argtypes = [_p, _i32]
@@ -171,6 +172,13 @@ def psweep_set_tile(ctx, level: int, rows_per_wave: int, waves: int):
 
 def psweep_set_chunks(ctx, level: int, n_chunks: int):
     _check(lib().psweep_set_chunks(ctx, level, n_chunks), ctx)
+
+
+def psweep_mask_boxes(ctx, camera_set: int, depth: int, code: int, pitch: int, boxes, stream: int = 0):
+    """boxes: sequence of (x0, y0, x1, y1) half-open pixel rectangles."""
+    flat = [int(v) for b in boxes for v in b]
+    arr = (_i32 * max(1, len(flat)))(*flat)
+    _check(lib().psweep_mask_boxes(ctx, camera_set, depth, code, pitch, len(flat) // 4, arr, stream), ctx)
 
 
 def psweep_filter(ctx, camera_set: int, maps: psweep_maps, params: psweep_filter_params, out_depth: int,

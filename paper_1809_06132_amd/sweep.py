@@ -216,6 +216,15 @@ class PlaneSweep:
                         _stream_handle(stream))
         return d, c
 
+    def mask_boxes(self, depth, boxes, code=None, camera_set=0, stream=None):
+        """Mask the pixels inside detected boxes (x0, y0, x1, y1; half-open)
+        out of a full-resolution depth map in place: depth NaN, code 4."""
+        assert depth.is_cuda and depth.dtype == torch.float32 and depth.stride(1) == 1
+        if code is not None:
+            assert code.is_cuda and code.dtype == torch.uint8 and code.stride(0) == depth.stride(0)
+        P.psweep_mask_boxes(self.ctx, camera_set, depth.data_ptr(), code.data_ptr() if code is not None else 0,
+                            depth.stride(0), boxes, _stream_handle(stream))
+
     def plane_pixels(self, frames) -> int:
         return P.psweep_plane_pixels(self.ctx, [self._frame(f) for f in frames])
 

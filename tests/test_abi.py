@@ -82,6 +82,7 @@ def test_null_arguments():
     assert L.psweep_workspace_size(None, None) == psweep.EINVAL
     assert L.psweep_run(None, None, 0, None, None) == psweep.EINVAL
     assert L.psweep_soft_depth_backward(None, None, None, None, None) == psweep.EINVAL
+    assert L.psweep_mask_boxes(None, 0, None, None, 0, 0, None, None) == psweep.EINVAL
 
 
 def test_product_path_is_independent_of_the_oracle():

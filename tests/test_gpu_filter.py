@@ -37,3 +37,37 @@ def test_filter_matches_oracle(window, ratio):
     keep = (gc == 0) & (oc == 0)
     assert np.array_equal(gd[keep], od[keep].astype(np.float32))
     assert np.all(np.isnan(gd[gc != 0]))
+
+
+def test_mask_boxes_after_filter():
+    """Detected boxes (some partly outside the image, overlapping, empty, and
+    more than one launch holds) masked out of the filtered map, against the
+    oracle's filter and mask."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+    wl = scenegen.workload("C1")
+    fr, st = wl.frames[0], wl.settings
+    ps = PlaneSweep(st, 320, 256, 1)
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    out = ps.alloc_outputs()
+    ps.run([frame_to_device(fr)], [out])
+    d, c = ps.filter(out["merged"])
+    rng = np.random.default_rng(5)
+    boxes = [(-20, -10, 40, 30), (300, 200, 400, 300), (100, 100, 100, 140), (50, 60, 120, 90), (70, 70, 130, 160)]
+    boxes += [tuple(int(v) for v in (x, y, x + rng.integers(1, 30), y + rng.integers(1, 30)))
+              for x, y in zip(rng.integers(-10, 320, 80), rng.integers(-10, 256, 80))]
+    ps.mask_boxes(d, boxes, code=c)
+    torch.cuda.synchronize()
+    gd, gc = d.cpu().numpy(), c.cpu().numpy()
+    m = {k: v.cpu().numpy() for k, v in out["merged"].items()}
+    ps.close()
+    od, oc = oracle.depth_filter(fr.ref_cam, st.ground_n, m["depth"].astype(np.float64),
+                                 m["cost1"].astype(np.float64), m["cost2"].astype(np.float64))
+    od, oc = oracle.mask_boxes(od, boxes, oc)
+    near = np.abs(m["cost2"].astype(np.float64) - 1.05 * m["cost1"]) <= 1e-6 * np.abs(m["cost2"])
+    assert ((gc != oc) & ~near).sum() == 0
+    assert np.all(gc[oc == 4] == 4)
+    keep = (gc == 0) & (oc == 0)
+    assert np.array_equal(gd[keep], od[keep].astype(np.float32))
+    assert np.all(np.isnan(gd[gc != 0]))

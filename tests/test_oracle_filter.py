@@ -104,3 +104,22 @@ def test_filters_reduce_error_on_a_scene():
     assert e_flt.mean() < 0.7 * e_raw.mean()
     assert np.median(e_flt) < np.median(e_raw)
     assert flt.sum() > 0.3 * raw.sum()
+
+
+def test_mask_boxes_definition():
+    """Box masking: every pixel of [x0, x1) x [y0, y1) and only those, parts
+    outside the image ignored, overlaps and empty boxes harmless."""
+    d = np.arange(24 * 32, dtype=np.float64).reshape(24, 32)
+    code = np.zeros((24, 32), np.uint8)
+    boxes = [(3, 4, 10, 9), (8, 7, 12, 12), (-5, -5, 2, 3), (30, 20, 40, 40), (5, 5, 5, 9)]
+    out, oc = oracle.mask_boxes(d, boxes, code)
+    keep = np.ones((24, 32), bool)
+    keep[4:9, 3:10] = False
+    keep[7:12, 8:12] = False
+    keep[0:3, 0:2] = False
+    keep[20:24, 30:32] = False
+    assert np.array_equal(np.isfinite(out), keep)
+    assert np.array_equal(out[keep], d[keep])
+    assert np.array_equal(oc == 4, ~keep) and np.all(oc[keep] == 0)
+    out2, _ = oracle.mask_boxes(d, [])
+    assert np.array_equal(out2, d)
