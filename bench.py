@@ -241,22 +241,27 @@ def bench_c4(args):
     fwd, fwd_pct = _time_runs(ps, [d], [out], args.steps, args.warmup)
     g = torch.randn((H, W), device="cuda", generator=torch.Generator(device="cuda").manual_seed(0))
     shapes = [s.shape for s in fr.srcs]
-    for _ in range(args.warmup):
-        ps.soft_backward(g, shapes)
-    torch.cuda.synchronize()
-    ms = []
-    for _ in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        ps.soft_backward(g, shapes)
-        e1.record()
+    def time_backward(image_grads):
+        for _ in range(args.warmup):
+            ps.soft_backward(g, shapes, image_grads=image_grads)
         torch.cuda.synchronize()
-        ms.append(e0.elapsed_time(e1))
+        ms = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ps.soft_backward(g, shapes, image_grads=image_grads)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms)), [float(v) for v in np.percentile(ms, [10, 50, 90])]
+
+    bwd, bwd_pct = time_backward(True)
+    bwd_pose, bwd_pose_pct = time_backward(False)
     ps.close()
-    bwd = float(np.median(ms))
     line = {"metric": METRIC, "workload": "C4", "plane_pixels": pp, "forward_ms": fwd,
             "forward_ms_p10_p50_p90": fwd_pct, "forward_gpix_planes_per_s": pp / (fwd * 1e-3) / 1e9,
-            "backward_ms": bwd, "backward_ms_p10_p50_p90": [float(v) for v in np.percentile(ms, [10, 50, 90])]}
+            "backward_ms": bwd, "backward_ms_p10_p50_p90": bwd_pct,
+            "backward_pose_only_ms": bwd_pose, "backward_pose_only_ms_p10_p50_p90": bwd_pose_pct}
     if not args.no_cpu:
         rect = (288, 216, 64, 48)
         rng = np.random.default_rng(0)

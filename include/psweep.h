@@ -194,7 +194,8 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
 /* Gradient of L = sum_p g_p * soft_invdepth_p (g = d_grad_invdepth, full
  * resolution, pitch soft_pitch of the last run) with respect to every source
  * image (d_grad_src[s]: float device array of the source's size, row-major,
- * overwritten) and to every source pose as a left perturbation X_src ->
+ * overwritten; a NULL d_grad_src, or a NULL entry, skips that image gradient
+ * and its atomics) and to every source pose as a left perturbation X_src ->
  * X_src + v + omega x X_src (d_grad_pose: device doubles [n_src][6] ordered
  * v, omega; overwritten).  Uses the images and soft outputs of the last
  * psweep_run, which must have been a soft run (ESTATE otherwise).  Warps are

@@ -75,8 +75,11 @@ class SoftDepth(torch.autograd.Function):
         g = grad_rho if grad_rho is not None else None
         if g is None:
             return (None, None, None) + tuple(None for _ in ctx.shapes)
-        gs, gp = ctx.sweep.soft_backward(g, ctx.shapes)
-        g_src = tuple(gsi if f else None for gsi, f in zip(gs, ctx.float_src))
+        # image gradients only for float sources that ask for them (inputs
+        # 0..2 are the sweep, the reference and the pose)
+        want = [f and ctx.needs_input_grad[3 + s] for s, f in enumerate(ctx.float_src)]
+        gs, gp = ctx.sweep.soft_backward(g, ctx.shapes, image_grads=want)
+        g_src = tuple(gs)
         return (None, None, gp.to(device=ctx.xi_device, dtype=ctx.xi_dtype)) + g_src
 
 

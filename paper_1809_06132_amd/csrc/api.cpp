@@ -26,6 +26,7 @@ extern "C" const void *psw_filter_kernel();
 extern "C" const void *psw_mask_kernel();
 extern "C" const void *psw_backward_kernel(int win, int n_src, int img);
 extern "C" size_t psw_backward_lds(int win, int n_src);
+extern "C" int psw_backward_tile_rows();
 extern "C" const void *psw_zero_kernel();
 
 namespace {
@@ -883,15 +884,17 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
                                          double *d_grad_pose, void *hip_stream) {
     if (!ctx) return PSWEEP_EINVAL;
     if (!ctx->soft_ready) return fail(ctx, PSWEEP_ESTATE, "backward needs a preceding soft-mode psweep_run");
-    if (!d_grad_invdepth || !d_grad_src || !d_grad_pose) return fail(ctx, PSWEEP_EINVAL, "NULL gradient buffer");
+    if (!d_grad_invdepth || !d_grad_pose) return fail(ctx, PSWEEP_EINVAL, "NULL gradient buffer");
     hipStream_t stream = (hipStream_t)hip_stream;
     const JobDev *job = (const JobDev *)(ctx->ws + ctx->soft_job_off);
     const CamSet &C = ctx->sets[ctx->soft_frame.camera_set];
-    for (int s = 0; s < C.n_src; ++s)
-        if (!d_grad_src[s]) return fail(ctx, PSWEEP_EINVAL, "NULL source gradient");
+    // source image gradients are optional: a NULL array or entry skips them
+    float *gsrc[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int s = 0; s < C.n_src; ++s) gsrc[s] = d_grad_src ? d_grad_src[s] : nullptr;
     const void *zk = psw_zero_kernel();
     for (int s = 0; s < C.n_src; ++s) {
-        float *p = d_grad_src[s];
+        float *p = gsrc[s];
+        if (!p) continue;
         int64_t n = (int64_t)C.src[s].width * C.src[s].height;
         void *a[] = {&p, &n};
         PSW_HIP(hipLaunchKernel(zk, dim3(256), dim3(256), a, 0, stream), "zero");
@@ -909,11 +912,11 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     if (lds > 65536) PSW_HIP(hipFuncSetAttribute(bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds limit");
     const int hw = win / 2;
     const int w = C.ref.width, h = C.ref.height;
+    const int tyo = psw_backward_tile_rows();
     const int tx = (w - 2 * hw + (kWave - 2 * hw) - 1) / (kWave - 2 * hw);
-    const int ty = (h - 2 * hw + 31) / 32;
+    const int ty = (h - 2 * hw + tyo - 1) / tyo;
     if (tx <= 0 || ty <= 0) return PSWEEP_OK;
-    float *g0 = d_grad_src[0], *g1 = C.n_src > 1 ? d_grad_src[1] : nullptr;
-    float *g2 = C.n_src > 2 ? d_grad_src[2] : nullptr, *g3 = C.n_src > 3 ? d_grad_src[3] : nullptr;
+    float *g0 = gsrc[0], *g1 = gsrc[1], *g2 = gsrc[2], *g3 = gsrc[3];
     const float *rho = ctx->soft_rho, *lse = ctx->soft_lse;
     int64_t sp = ctx->soft_pitch;
     void *a[] = {(void *)&job, (void *)&d_grad_invdepth, (void *)&rho, (void *)&lse, &sp,

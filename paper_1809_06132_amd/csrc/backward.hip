@@ -16,10 +16,13 @@
 // Each sample's gradient then goes through the bilinear interpolant to the
 // four source texels (atomics) and through the projection to the pose.
 //
-// Tile layout as in the forward sweep: 4 waves, lane = sample column, 8 output
-// rows per wave; per plane the warped rows go to LDS, the four channels of
-// every output pixel go to LDS, and every wave then handles its own sample
-// rows (interleaved across waves, as in the warp phase).
+// Tile layout: 4 waves, lane = sample column, 4 output rows per wave (the
+// four channels of every output pixel then fit in 32 KB of LDS for two
+// sources, so several workgroups share a CU).  Every wave owns a contiguous
+// block of the tile's sample rows: it warps them into LDS, and after the
+// channels are written it walks down the block keeping running sums of the
+// channels over the output rows whose window holds the current sample row
+// (one row added, one dropped per step).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -36,12 +39,12 @@ __global__ void zero_kernel(float *p, int64_t n) {
 
 template <int WIN, int S, int IMG>
 struct Backward {
-    static constexpr int NW = 4, R = 8;
+    static constexpr int NW = 4, R = 4;
     static constexpr int HW = WIN / 2;
     static constexpr int TXO = kWave - 2 * HW;
     static constexpr int TYO = NW * R;
     static constexpr int T = TYO + 2 * HW;
-    static constexpr int NWR = (T + NW - 1) / NW;
+    static constexpr int RS = (T + NW - 1) / NW;   // contiguous sample rows per wave
     static constexpr int VR = R + 2 * HW;
     static constexpr int NCH = 4;
 
@@ -67,11 +70,12 @@ struct Backward {
         Shifts sh;
         sh.init(lane);
 
-        // sample rows this wave warps (and later scatters)
-        float yw[NWR], tf[NWR], aw[NWR];
+        // sample rows this wave warps (and later scatters): j0 .. j0 + RS - 1
+        const int j0 = wave * RS;
+        float yw[RS], tf[RS], aw[RS];
 #pragma unroll
-        for (int i = 0; i < NWR; ++i) {
-            const int v = sr0 + wave + NW * i;
+        for (int i = 0; i < RS; ++i) {
+            const int v = sr0 + j0 + i;
             yw[i] = ((float)v - J.cy) * J.inv_fy;
             const float t = ray_tau(x, yw[i], xi, nullptr);
             tf[i] = t > 0.0f ? t : __builtin_nanf("");
@@ -148,9 +152,9 @@ struct Backward {
                     (void *)sd.tex, (short)0, (int)(row_bytes * (uint32_t)sd.h), 0x00020000);
                 const float px = h1x * x, py = h1y * x, pz = h1z * x;
 #pragma unroll
-                for (int i = 0; i < NWR; ++i) {
-                    const int j = wave + NW * i;
-                    if (i == NWR - 1 && j >= T) break;
+                for (int i = 0; i < RS; ++i) {
+                    const int j = j0 + i;
+                    if (j >= T) break;   // the last wave's block is shorter
                     const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
                     const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
                     const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
@@ -255,21 +259,31 @@ struct Backward {
                     (void *)sd.tex, (short)0, (int)(row_bytes * (uint32_t)sd.h), 0x00020000);
                 const float px = h1x * x, py = h1y * x, pz = h1z * x;
                 float *gimg = gsrc[s];
+                // running sums of the channels over the output rows whose
+                // window holds sample row j: rows [j - 2 HW, j] within the tile
+                const float *chs = chan + ((size_t)s * NCH) * TYO * kWave + lane;
+                float rA = 0.f, rB = 0.f, rC = 0.f, rE = 0.f;
+                for (int r = j0 - 1 - 2 * HW < 0 ? 0 : j0 - 1 - 2 * HW; r <= j0 - 1 && r < TYO; ++r) {
+                    const float *ch = chs + (size_t)r * kWave;
+                    rA += ch[0]; rB += ch[(size_t)TYO * kWave];
+                    rC += ch[(size_t)2 * TYO * kWave]; rE += ch[(size_t)3 * TYO * kWave];
+                }
 #pragma unroll
-                for (int i = 0; i < NWR; ++i) {
-                    const int j = wave + NW * i;
-                    if (i == NWR - 1 && j >= T) break;
-                    // output rows whose window holds sample row j: [j - 2 HW, j]
-                    float sA = 0.f, sB = 0.f, sC = 0.f, sE = 0.f;
-                    const int lo = j - 2 * HW < 0 ? 0 : j - 2 * HW;
-                    const int hi = j < TYO - 1 ? j : TYO - 1;
-                    for (int r = lo; r <= hi; ++r) {
-                        const float *ch = chan + (((size_t)s * NCH) * TYO + r) * kWave + lane;
-                        sA += ch[0]; sB += ch[(size_t)TYO * kWave];
-                        sC += ch[(size_t)2 * TYO * kWave]; sE += ch[(size_t)3 * TYO * kWave];
+                for (int i = 0; i < RS; ++i) {
+                    const int j = j0 + i;
+                    if (j >= T) break;
+                    if (j < TYO) {
+                        const float *ch = chs + (size_t)j * kWave;
+                        rA += ch[0]; rB += ch[(size_t)TYO * kWave];
+                        rC += ch[(size_t)2 * TYO * kWave]; rE += ch[(size_t)3 * TYO * kWave];
                     }
-                    sA = wsum<WIN>(sA, sh); sB = wsum<WIN>(sB, sh);
-                    sC = wsum<WIN>(sC, sh); sE = wsum<WIN>(sE, sh);
+                    if (j - 2 * HW - 1 >= 0) {
+                        const float *ch = chs + (size_t)(j - 2 * HW - 1) * kWave;
+                        rA -= ch[0]; rB -= ch[(size_t)TYO * kWave];
+                        rC -= ch[(size_t)2 * TYO * kWave]; rE -= ch[(size_t)3 * TYO * kWave];
+                    }
+                    const float sA = wsum<WIN>(rA, sh), sB = wsum<WIN>(rB, sh);
+                    const float sC = wsum<WIN>(rC, sh), sE = wsum<WIN>(rE, sh);
                     const float b = tile[((size_t)s * T + j) * kWave + lane];
                     const float gb = fmaf(aw[i], sA, -sB) + fmaf(-b, sC, sE);
                     if (gb == 0.0f || is_neg_zero(b)) continue;
@@ -282,17 +296,18 @@ struct Backward {
                     const float inv = __builtin_amdgcn_rcpf(den);
                     const float u = fmaf(X * inv, sd.fx, sd.cx);
                     const float v = fmaf(Y * inv, sd.fy, sd.cy);
-                    const int i0 = (int)u, j0 = (int)v;
+                    const int i0 = (int)u, v0 = (int)v;
                     const int i1 = i0 + 1 < sd.w ? i0 + 1 : sd.w - 1;
-                    const int j1 = j0 + 1 < sd.h ? j0 + 1 : sd.h - 1;
-                    const float al = u - (float)i0, be = v - (float)j0;
-                    const auto q = Texel<IMG>::load(rs, __umul24((uint32_t)j0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes);
+                    const int v1 = v0 + 1 < sd.h ? v0 + 1 : sd.h - 1;
+                    const float al = u - (float)i0, be = v - (float)v0;
+                    const auto q = Texel<IMG>::load(rs, __umul24((uint32_t)v0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes);
                     const float p00 = q.p00, p10 = q.p10, p01 = q.p01, p11 = q.p11;
-                    float *gi = gimg;
-                    atomicAdd(gi + (int64_t)j0 * sd.w + i0, gb * (1.0f - al) * (1.0f - be));
-                    atomicAdd(gi + (int64_t)j0 * sd.w + i1, gb * al * (1.0f - be));
-                    atomicAdd(gi + (int64_t)j1 * sd.w + i0, gb * (1.0f - al) * be);
-                    atomicAdd(gi + (int64_t)j1 * sd.w + i1, gb * al * be);
+                    if (gimg) {   // image gradient requested for this source
+                        atomicAdd(gimg + (int64_t)v0 * sd.w + i0, gb * (1.0f - al) * (1.0f - be));
+                        atomicAdd(gimg + (int64_t)v0 * sd.w + i1, gb * al * (1.0f - be));
+                        atomicAdd(gimg + (int64_t)v1 * sd.w + i0, gb * (1.0f - al) * be);
+                        atomicAdd(gimg + (int64_t)v1 * sd.w + i1, gb * al * be);
+                    }
                     const float dbu = fmaf(be, p11 - p01, (1.0f - be) * (p10 - p00));
                     const float dbv = fmaf(al, p11 - p10, (1.0f - al) * (p01 - p00));
                     // (X, Y, Z) = H (x, y, tau) is the source point divided by
@@ -359,6 +374,8 @@ const void *psw_backward_kernel(int win, int n_src, int img) {
 #undef PSW_B
     return nullptr;
 }
+
+int psw_backward_tile_rows() { return psw::Backward<5, 1, 0>::TYO; }
 
 size_t psw_backward_lds(int win, int n_src) {
 #define PSW_L(W)                                                       \

@@ -228,14 +228,18 @@ class PlaneSweep:
     def plane_pixels(self, frames) -> int:
         return P.psweep_plane_pixels(self.ctx, [self._frame(f) for f in frames])
 
-    def soft_backward(self, grad_invdepth, src_shapes, stream=None):
+    def soft_backward(self, grad_invdepth, src_shapes, stream=None, image_grads=True):
         """Gradients of sum(grad * soft_invdepth) of the last soft run: list of
-        per-source image gradients and a [S, 6] float64 pose gradient (v, omega)."""
+        per-source image gradients (None where not requested) and a [S, 6]
+        float64 pose gradient (v, omega).  image_grads: True, False, or one
+        flag per source."""
         g = grad_invdepth.contiguous().float()
-        gs = [torch.empty(s, dtype=torch.float32, device=self.device) for s in src_shapes]
+        want = [image_grads] * len(src_shapes) if isinstance(image_grads, bool) else list(image_grads)
+        gs = [torch.empty(s, dtype=torch.float32, device=self.device) if w else None
+              for s, w in zip(src_shapes, want)]
         gp = torch.empty((len(src_shapes), 6), dtype=torch.float64, device=self.device)
-        P.psweep_soft_depth_backward(self.ctx, g.data_ptr(), [t.data_ptr() for t in gs], gp.data_ptr(),
-                                     _stream_handle(stream))
+        P.psweep_soft_depth_backward(self.ctx, g.data_ptr(), [t.data_ptr() if t is not None else None for t in gs],
+                                     gp.data_ptr(), _stream_handle(stream))
         return gs, gp
 
 

@@ -199,3 +199,26 @@ def test_soft_backward_matches_oracle_gradient(case):
     print(case, "pose", gp, ogp, "rel", rel_pose, "img rel", rel_img)
     assert np.linalg.norm(ogp) > 0
     assert rel_pose <= 1e-3 and rel_img <= 1e-3
+
+
+def test_soft_backward_pose_only_matches_full():
+    """Skipping the image gradients (NULL source-gradient pointers) leaves the
+    pose gradient unchanged."""
+    PlaneSweep, frame_to_device = _gpu()
+    fr, lv, st = _soft_case()
+    ps = PlaneSweep(st, 64, 48, 2)
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    out = ps.alloc_outputs()
+    ps.run([frame_to_device(fr)], [out])
+    g = torch.from_numpy(np.random.default_rng(2).normal(size=(48, 64)).astype(np.float32)).cuda()
+    shapes = [s.shape for s in fr.srcs]
+    gs, gp = ps.soft_backward(g, shapes)
+    gs0, gp0 = ps.soft_backward(g, shapes, image_grads=False)
+    gs1, gp1 = ps.soft_backward(g, shapes, image_grads=[False, True])
+    torch.cuda.synchronize()
+    ps.close()
+    assert gs0 == [None, None] and gs1[0] is None
+    a, b, c = gp.cpu().numpy(), gp0.cpu().numpy(), gp1.cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max() + 1e-12
+    assert np.abs(a - c).max() <= 1e-9 * np.abs(a).max() + 1e-12
+    assert torch.allclose(gs[1], gs1[1], rtol=1e-5, atol=1e-7)
