@@ -35,10 +35,10 @@ _p = ctypes.c_void_p
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, strict IEEE double)."""
     if force or not os.path.exists(_LIB_PATH):
-        src = os.path.join(_HERE, "psweep_oracle.c")
+        srcs = [os.path.join(_HERE, "psweep_oracle.c"), os.path.join(_HERE, "tsdf_oracle.c")]
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-                               "-shared", "-fPIC", src, "-o", tmp, "-lm"])
+                               "-shared", "-fPIC", *srcs, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -99,6 +99,12 @@ def lib():
     L.or_filter.restype = None
     L.or_threads.argtypes = []
     L.or_threads.restype = _i32
+    L.or_tsdf_alloc.argtypes = [PC, PP, _p, _i64, _d, _d, _p, _p, _p, _p]
+    L.or_tsdf_alloc.restype = None
+    L.or_tsdf_visible.argtypes = [PC, PP, _d, _p, _p, _p, _p, _p]
+    L.or_tsdf_visible.restype = None
+    L.or_tsdf_integrate.argtypes = [PC, PP, _p, _i64, _d, _d, _d, _p, _p, _p, _p, _p, _p]
+    L.or_tsdf_integrate.restype = None
     return L
 
 
@@ -425,3 +431,85 @@ def mask_boxes(depth, boxes, code=None):
                 if c is not None:
                     c[y, x] = 4
     return d, c
+
+
+# ----------------------------------------------------------------------------
+# TSDF depth-map fusion (Sec. III-C, Eq. (1)-(2))
+# ----------------------------------------------------------------------------
+def tsdf_region(centre, voxel, nb):
+    """First block (integer block coordinates) of the box of nb blocks centred
+    on `centre` (world metres): floor(centre / B) - nb // 2 per axis."""
+    B = 8.0 * voxel
+    return np.array([int(np.floor(c / B)) - n // 2 for c, n in zip(centre, nb)], np.int32)
+
+
+class TsdfOracle:
+    """The local map as plain arrays over a box of nb = (nbx, nby, nbz) blocks
+    of 8^3 voxels that follows a centre point.  D starts at 1 and w at 0; a
+    block's observation count is the number of fused depth maps whose rays met
+    it; blocks leave the map (cleared) when the box moves past them."""
+
+    def __init__(self, voxel, mu, nb, w_max=100.0, min_obs=3):
+        self.voxel, self.mu, self.w_max, self.min_obs = float(voxel), float(mu), float(w_max), int(min_obs)
+        self.nb = np.array(nb, np.int32)
+        self.b0 = None
+        nbz, nby, nbx = self.nb[2], self.nb[1], self.nb[0]
+        self.alloc = np.zeros((nbz, nby, nbx), np.int32)
+        self.count = np.zeros((nbz, nby, nbx), np.int32)
+        self.D = np.ones((nbz * 8, nby * 8, nbx * 8))
+        self.W = np.zeros((nbz * 8, nby * 8, nbx * 8))
+
+    def set_centre(self, centre):
+        b0 = tsdf_region(centre, self.voxel, self.nb)
+        if self.b0 is not None and not np.array_equal(b0, self.b0):
+            sh = b0 - self.b0      # blocks the box moved by (x, y, z)
+            for name, scale, fill in (("alloc", 1, 0), ("count", 1, 0), ("D", 8, 1.0), ("W", 8, 0.0)):
+                a = getattr(self, name)
+                out = np.full_like(a, fill)
+                src = [slice(None)] * 3
+                dst = [slice(None)] * 3
+                for ax, s in zip((2, 1, 0), sh):   # array axes are z, y, x
+                    n = a.shape[ax]
+                    k = int(s) * scale
+                    if abs(k) >= n:
+                        src[ax] = slice(0, 0); dst[ax] = slice(0, 0)
+                    elif k >= 0:
+                        src[ax] = slice(k, n); dst[ax] = slice(0, n - k)
+                    else:
+                        src[ax] = slice(0, n + k); dst[ax] = slice(-k, n)
+                out[tuple(dst)] = a[tuple(src)]
+                setattr(self, name, out)
+        self.b0 = b0
+
+    def integrate(self, cam, cam_pose, depth, centre):
+        """Fuse one depth map (range along the Eq. (1) ray; NaN = invalid)
+        taken with `cam_pose` (X_cam = R X_world + t).  Returns the per-step
+        diagnostics: touched blocks, their longest segment piece, visible
+        blocks, visibility and voxel edge flags."""
+        self.set_centre(centre)
+        dep = np.ascontiguousarray(np.asarray(depth, np.float64))
+        h, w = dep.shape
+        c, p = camera(cam), pose(cam_pose)
+        b0 = np.ascontiguousarray(self.b0)
+        nb = np.ascontiguousarray(self.nb)
+        touched = np.zeros_like(self.alloc)
+        pen = np.zeros(self.alloc.shape)
+        lib().or_tsdf_alloc(ctypes.byref(c), ctypes.byref(p), dep.ctypes.data, w, self.voxel, self.mu,
+                            b0.ctypes.data, nb.ctypes.data, touched.ctypes.data, pen.ctypes.data)
+        self.alloc |= touched
+        self.count += touched
+        vis = np.zeros_like(self.alloc)
+        vedge = np.zeros_like(self.alloc)
+        lib().or_tsdf_visible(ctypes.byref(c), ctypes.byref(p), self.voxel, b0.ctypes.data, nb.ctypes.data,
+                              self.alloc.ctypes.data, vis.ctypes.data, vedge.ctypes.data)
+        edge = np.zeros(self.D.shape, np.int32)
+        lib().or_tsdf_integrate(ctypes.byref(c), ctypes.byref(p), dep.ctypes.data, w, self.voxel, self.mu,
+                                self.w_max, b0.ctypes.data, nb.ctypes.data, vis.ctypes.data,
+                                self.D.ctypes.data, self.W.ctypes.data, edge.ctypes.data)
+        return {"touched": touched, "pen": pen, "visible": vis, "vis_edge": vedge, "voxel_edge": edge}
+
+    def extract(self):
+        """D where the voxel was observed and its block has at least min_obs
+        observations; NaN elsewhere (Sec. III-C)."""
+        ok_blk = np.repeat(np.repeat(np.repeat(self.count >= self.min_obs, 8, 0), 8, 1), 8, 2)
+        return np.where(ok_blk & (self.W > 0), self.D, np.nan)
