@@ -443,6 +443,29 @@ def tsdf_region(centre, voxel, nb):
     return np.array([int(np.floor(c / B)) - n // 2 for c, n in zip(centre, nb)], np.int32)
 
 
+def tsdf_shift(a, sh, scale, fill):
+    """Array `a` over a [z][y][x] box (scale cells per block) after the box
+    moved by sh = (x, y, z) blocks: what stays in the box keeps its world
+    place, the rest is `fill`."""
+    out = np.full_like(a, fill)
+    src = [slice(None)] * 3
+    dst = [slice(None)] * 3
+    for ax, s in zip((2, 1, 0), sh):   # array axes are z, y, x
+        n = a.shape[ax]
+        k = int(s) * scale
+        if abs(k) >= n:
+            src[ax] = slice(0, 0)
+            dst[ax] = slice(0, 0)
+        elif k >= 0:
+            src[ax] = slice(k, n)
+            dst[ax] = slice(0, n - k)
+        else:
+            src[ax] = slice(0, n + k)
+            dst[ax] = slice(-k, n)
+    out[tuple(dst)] = a[tuple(src)]
+    return out
+
+
 class TsdfOracle:
     """The local map as plain arrays over a box of nb = (nbx, nby, nbz) blocks
     of 8^3 voxels that follows a centre point.  D starts at 1 and w at 0; a
@@ -464,21 +487,7 @@ class TsdfOracle:
         if self.b0 is not None and not np.array_equal(b0, self.b0):
             sh = b0 - self.b0      # blocks the box moved by (x, y, z)
             for name, scale, fill in (("alloc", 1, 0), ("count", 1, 0), ("D", 8, 1.0), ("W", 8, 0.0)):
-                a = getattr(self, name)
-                out = np.full_like(a, fill)
-                src = [slice(None)] * 3
-                dst = [slice(None)] * 3
-                for ax, s in zip((2, 1, 0), sh):   # array axes are z, y, x
-                    n = a.shape[ax]
-                    k = int(s) * scale
-                    if abs(k) >= n:
-                        src[ax] = slice(0, 0); dst[ax] = slice(0, 0)
-                    elif k >= 0:
-                        src[ax] = slice(k, n); dst[ax] = slice(0, n - k)
-                    else:
-                        src[ax] = slice(0, n + k); dst[ax] = slice(-k, n)
-                out[tuple(dst)] = a[tuple(src)]
-                setattr(self, name, out)
+                setattr(self, name, tsdf_shift(getattr(self, name), sh, scale, fill))
         self.b0 = b0
 
     def integrate(self, cam, cam_pose, depth, centre):

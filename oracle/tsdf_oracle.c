@@ -50,15 +50,15 @@ static void to_cam(const ot_pose *p, const double Xw[3], double Xc[3])
         Xc[i] = p->R[i * 3 + 0] * Xw[0] + p->R[i * 3 + 1] * Xw[1] + p->R[i * 3 + 2] * Xw[2] + p->t[i];
 }
 
-/* Length of the part of segment A + s (B - A), s in [0, 1], inside the closed
- * box [lo, hi]; -1 when they do not meet (slab test). */
+/* Whether segment A + s (B - A), s in [0, 1], meets the closed box [lo, hi]
+ * (slab test); if so, how deep it reaches into the box: the largest distance
+ * from a point of its piece inside the box to the nearest face (0 for a
+ * segment that only touches the box or runs along a face), else -1. */
 static double seg_in_box(const double A[3], const double Bp[3], const double lo[3], const double hi[3])
 {
     double s0 = 0.0, s1 = 1.0;
-    double len2 = 0.0;
     for (int a = 0; a < 3; ++a) {
         double d = Bp[a] - A[a];
-        len2 += d * d;
         if (d == 0.0) {
             if (A[a] < lo[a] || A[a] > hi[a]) return -1.0;
             continue;
@@ -69,12 +69,23 @@ static double seg_in_box(const double A[3], const double Bp[3], const double lo[
         if (tb < s1) s1 = tb;
         if (s0 > s1) return -1.0;
     }
-    return (s1 - s0) * sqrt(len2);
+    /* the distance to the nearest face is concave along the piece: sample it */
+    double best = 0.0;
+    for (int k = 0; k <= 64; ++k) {
+        double s = s0 + (s1 - s0) * k / 64.0, inner = 1e300;
+        for (int a = 0; a < 3; ++a) {
+            double p = A[a] + s * (Bp[a] - A[a]);
+            double m = p - lo[a] < hi[a] - p ? p - lo[a] : hi[a] - p;
+            if (m < inner) inner = m;
+        }
+        if (inner > best) best = inner;
+    }
+    return best;
 }
 
 /* Step 1.  touched[nb]: 1 for every block met by some pixel's segment;
- * pen[nb]: the longest piece of any segment inside the block (metres), for
- * telling blocks that are only grazed. */
+ * pen[nb]: the deepest any segment reaches into the block (metres, see
+ * seg_in_box), for telling blocks that are only grazed. */
 void or_tsdf_alloc(const ot_camera *cam, const ot_pose *pose, const double *depth, int64_t pitch, double voxel,
                    double mu, const int32_t b0[3], const int32_t nb[3], int32_t *touched, double *pen)
 {
@@ -114,8 +125,8 @@ void or_tsdf_alloc(const ot_camera *cam, const ot_pose *pose, const double *dept
 }
 
 /* Step 2.  vis[nb]: allocated blocks with a corner that projects into
- * [0, W-1] x [0, H-1].  edge[nb]: 1 where the nearest corner projection lies
- * within 1e-6 px of that border (a decision FP32 may take the other way). */
+ * [0, W-1] x [0, H-1].  edge[nb]: 1 where a corner projection lies within
+ * 1e-2 px of that border (a decision FP32 arithmetic may take the other way). */
 void or_tsdf_visible(const ot_camera *cam, const ot_pose *pose, double voxel, const int32_t b0[3],
                      const int32_t nb[3], const int32_t *alloc, int32_t *vis, int32_t *edge)
 {
@@ -134,15 +145,16 @@ void or_tsdf_visible(const ot_camera *cam, const ot_pose *pose, double voxel, co
                     to_cam(pose, Xw, Xc);
                     if (!or_project(cam, Xc, &u, &v)) continue;
                     double m = fmin(fmin(u, cam->width - 1 - u), fmin(v, cam->height - 1 - v));
-                    if (fabs(m) < 1e-6) edge[i] = 1;
+                    if (fabs(m) < 1e-2) edge[i] = 1;
                     if (m >= 0.0) vis[i] = 1;
                 }
             }
 }
 
 /* Step 3 (Eq. (2)).  D, W over the box's voxel grid.  edge_vox: 1 where the
- * voxel's update is decided within a rounding of the pixel choice (a
- * projection within 1e-4 px of a pixel boundary) or of the eta >= -mu test. */
+ * voxel's update is decided within FP32 rounding of the pixel choice (a
+ * projection within 2e-3 px of a pixel boundary) or of the eta >= -mu test
+ * (within 1e-3 m). */
 void or_tsdf_integrate(const ot_camera *cam, const ot_pose *pose, const double *depth, int64_t pitch, double voxel,
                        double mu, double w_max, const int32_t b0[3], const int32_t nb[3], const int32_t *vis,
                        double *D, double *W, int32_t *edge_vox)
@@ -161,15 +173,15 @@ void or_tsdf_integrate(const ot_camera *cam, const ot_pose *pose, const double *
                 to_cam(pose, Xw, Xc);
                 if (!or_project(cam, Xc, &u, &v)) continue;
                 double fu = floor(u + 0.5), fv = floor(v + 0.5);
-                if (fabs(u + 0.5 - fu) < 1e-4 || fabs(u + 0.5 - fu - 1.0) < 1e-4 ||
-                    fabs(v + 0.5 - fv) < 1e-4 || fabs(v + 0.5 - fv - 1.0) < 1e-4)
+                if (fabs(u + 0.5 - fu) < 2e-3 || fabs(u + 0.5 - fu - 1.0) < 2e-3 ||
+                    fabs(v + 0.5 - fv) < 2e-3 || fabs(v + 0.5 - fv - 1.0) < 2e-3)
                     edge_vox[o] = 1;
                 if (fu < 0 || fv < 0 || fu > cam->width - 1 || fv > cam->height - 1) continue;
                 double d_obs = depth[(int64_t)fv * pitch + (int64_t)fu];
                 if (!(d_obs > 0.0) || !isfinite(d_obs)) continue;
                 double range = sqrt(Xc[0] * Xc[0] + Xc[1] * Xc[1] + Xc[2] * Xc[2]);
                 double eta = d_obs - range;
-                if (fabs(eta + mu) < 1e-4) edge_vox[o] = 1;
+                if (fabs(eta + mu) < 1e-3) edge_vox[o] = 1;
                 if (eta < -mu) continue;
                 double f = eta / mu < 1.0 ? eta / mu : 1.0;
                 D[o] = (W[o] * D[o] + f) / (W[o] + 1.0);

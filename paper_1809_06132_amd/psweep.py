@@ -27,7 +27,10 @@ EXPORTS = ["psweep_create", "psweep_workspace_size", "psweep_set_workspace", "ps
            "psweep_set_crop", "psweep_run", "psweep_soft_depth_backward", "psweep_set_tile",
            "psweep_graph_capture", "psweep_graph_launch", "psweep_set_timing", "psweep_sweep_kernel_ms",
            "psweep_sweep_kernel_times", "psweep_set_chunks", "psweep_filter", "psweep_mask_boxes",
-           "psweep_plane_pixels", "psweep_destroy", "psweep_last_error", "psweep_version"]
+           "psweep_plane_pixels", "psweep_destroy", "psweep_last_error", "psweep_version",
+           "psweep_tsdf_create", "psweep_tsdf_workspace_size", "psweep_tsdf_set_workspace", "psweep_tsdf_reset",
+           "psweep_tsdf_integrate", "psweep_tsdf_extract", "psweep_tsdf_region", "psweep_tsdf_stats",
+           "psweep_tsdf_last_error", "psweep_tsdf_destroy"]
 
 
 class PsweepError(RuntimeError):
@@ -72,6 +75,11 @@ class psweep_filter_params(ctypes.Structure):
                 ("window", _i32)]
 
 
+class psweep_tsdf_config(ctypes.Structure):
+    _fields_ = [("voxel_m", _d), ("mu_m", _d), ("blocks", _i32 * 3), ("w_max", _d), ("min_observations", _i32),
+                ("max_width", _i32), ("max_height", _i32)]
+
+
 class psweep_output(ctypes.Structure):
     _fields_ = [("merged", psweep_maps), ("level", psweep_maps * MAX_LEVELS), ("soft_invdepth", _p),
                 ("soft_lse", _p), ("soft_pitch", _i64)]
@@ -96,6 +104,18 @@ def lib() -> ctypes.CDLL:
     L.psweep_set_chunks.argtypes = [_p, _i32, _i32]
     L.psweep_filter.argtypes = [_p, _i32, P(psweep_maps), P(psweep_filter_params), _p, _p, _i64, _p]
     L.psweep_mask_boxes.argtypes = [_p, _i32, _p, _p, _i64, _i32, P(_i32), _p]
+    L.psweep_tsdf_create.argtypes = [P(psweep_tsdf_config), P(_p)]
+    L.psweep_tsdf_workspace_size.argtypes = [_p, P(ctypes.c_size_t)]
+    L.psweep_tsdf_set_workspace.argtypes = [_p, _p, ctypes.c_size_t]
+    L.psweep_tsdf_reset.argtypes = [_p, _p]
+    L.psweep_tsdf_integrate.argtypes = [_p, P(psweep_camera), P(psweep_pose), P(_d), _p, _i64, _p]
+    L.psweep_tsdf_extract.argtypes = [_p, _p, _p, _p, _p]
+    L.psweep_tsdf_region.argtypes = [_p, P(_i32)]
+    L.psweep_tsdf_stats.argtypes = [_p, _p, _p]
+    L.psweep_tsdf_last_error.argtypes = [_p]
+    L.psweep_tsdf_last_error.restype = ctypes.c_char_p
+    L.psweep_tsdf_destroy.argtypes = [_p]
+    L.psweep_tsdf_destroy.restype = None
     L.psweep_graph_capture.argtypes = [_p, P(psweep_frame), _i32, P(psweep_output), _p]
     L.psweep_graph_launch.argtypes = [_p, _p]
     L.psweep_set_timing.argtypes = [_p, _i32]
@@ -109,7 +129,8 @@ def lib() -> ctypes.CDLL:
     L.psweep_version.argtypes = []
     L.psweep_version.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("psweep_destroy", "psweep_last_error", "psweep_version"):
+        if name not in ("psweep_destroy", "psweep_last_error", "psweep_version", "psweep_tsdf_destroy",
+                        "psweep_tsdf_last_error"):
             getattr(L, name).restype = _i32
     return L
 
@@ -225,3 +246,59 @@ def psweep_plane_pixels(ctx, frames) -> int:
 
 def psweep_destroy(ctx):
     lib().psweep_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# TSDF fusion (include/psweep_tsdf.h)
+# ---------------------------------------------------------------------------
+def _tcheck(st: int, ts=None):
+    if st != OK:
+        raise PsweepError(st, (lib().psweep_tsdf_last_error(ts) or b"").decode())
+
+
+def psweep_tsdf_create(cfg: psweep_tsdf_config):
+    h = _p()
+    _tcheck(lib().psweep_tsdf_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def psweep_tsdf_workspace_size(ts) -> int:
+    n = ctypes.c_size_t()
+    _tcheck(lib().psweep_tsdf_workspace_size(ts, ctypes.byref(n)), ts)
+    return n.value
+
+
+def psweep_tsdf_set_workspace(ts, ptr: int, nbytes: int):
+    _tcheck(lib().psweep_tsdf_set_workspace(ts, ptr, nbytes), ts)
+
+
+def psweep_tsdf_reset(ts, stream: int = 0):
+    _tcheck(lib().psweep_tsdf_reset(ts, stream), ts)
+
+
+def psweep_tsdf_integrate(ts, cam: psweep_camera, pose: psweep_pose, centre, depth: int, pitch: int,
+                          stream: int = 0):
+    c = (_d * 3)(*[float(v) for v in centre])
+    _tcheck(lib().psweep_tsdf_integrate(ts, ctypes.byref(cam), ctypes.byref(pose), c, depth, pitch, stream), ts)
+
+
+def psweep_tsdf_extract(ts, d_tsdf: int, d_weight: int, d_count: int, stream: int = 0):
+    _tcheck(lib().psweep_tsdf_extract(ts, d_tsdf, d_weight, d_count, stream), ts)
+
+
+def psweep_tsdf_region(ts):
+    b = (_i32 * 3)()
+    _tcheck(lib().psweep_tsdf_region(ts, b), ts)
+    return [int(v) for v in b]
+
+
+def psweep_tsdf_stats(ts, d_stats: int, stream: int = 0):
+    _tcheck(lib().psweep_tsdf_stats(ts, d_stats, stream), ts)
+
+
+def psweep_tsdf_last_error(ts) -> str:
+    return (lib().psweep_tsdf_last_error(ts) or b"").decode()
+
+
+def psweep_tsdf_destroy(ts):
+    lib().psweep_tsdf_destroy(ts)

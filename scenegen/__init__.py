@@ -385,6 +385,36 @@ def _paper(ss=4) -> Workload:
     return Workload("paper", [fr], paper_settings(), {"scene": 1006, "rig": 2006})
 
 
+@dataclass
+class DepthSequence:
+    """Depth maps of one scene from a vehicle driving forward: the camera, per
+    frame the pose world -> camera (the world is the first camera's frame),
+    the vehicle position and the ground-truth range map (float32 metres along
+    the Eq. (1) ray; NaN where nothing is hit)."""
+    cam: Camera
+    poses: list
+    centres: list
+    depths: list
+
+
+def depth_sequence(n_frames=6, w=320, h=240, f=None, step_m=0.5, seed=1007, yaw_deg=2.0, ss=1) -> DepthSequence:
+    """A street scene (ground, facades, boxes) seen from camera positions
+    step_m apart along z, each turned by a small seeded yaw."""
+    rng = np.random.default_rng(seed)
+    sc = _boxes_scene(rng, 20, 2.0, 40.0, -5.0, 5.0, facades=True)
+    cam = _fisheye(w, h, f if f is not None else 0.3516 * w)
+    poses, centres, depths = [], [], []
+    for k in range(n_frames):
+        yaw = math.radians(rng.uniform(-yaw_deg, yaw_deg))
+        Rcw = np.array([[math.cos(yaw), 0.0, math.sin(yaw)], [0.0, 1.0, 0.0], [-math.sin(yaw), 0.0, math.cos(yaw)]])
+        c = (0.0, 0.0, k * step_m)
+        _, rng_map, _ = sc.render(cam, Rcw, c, ss=ss, with_gt=True)
+        poses.append(_pose_from(Rcw, c))
+        centres.append(c)
+        depths.append(rng_map.astype(np.float32))
+    return DepthSequence(cam, poses, centres, depths)
+
+
 _MAKERS = {"C1": _c1, "C2": _c2, "C3": _c3, "C4": _c4, "C5": _c5, "paper": _paper}
 
 

@@ -16,8 +16,14 @@ def _lib_or_skip():
     return psweep
 
 
+def _declared():
+    import glob
+    text = "".join(open(h).read() for h in glob.glob(os.path.join(ROOT, "include", "*.h")))
+    return set(re.findall(r"\b(psweep_[a-z_]+)\s*\(", text))
+
+
 def test_header_and_binding_agree():
-    decl = set(re.findall(r"\b(psweep_[a-z_]+)\s*\(", open(HEADER).read()))
+    decl = _declared()
     from paper_1809_06132_amd import psweep
     assert decl == set(psweep.EXPORTS), decl ^ set(psweep.EXPORTS)
 
@@ -97,3 +103,27 @@ def test_product_path_is_independent_of_the_oracle():
     otext = open(os.path.join(ROOT, "oracle", "psweep_oracle.c")).read()
     assert "#include \"" not in otext and "psw::" not in otext
     assert "paper_1809_06132_amd" not in open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+
+
+def test_tsdf_rejects_bad_config():
+    psweep = _lib_or_skip()
+    def cfg(**kw):
+        c = psweep.psweep_tsdf_config(0.1, 0.3, (psweep._i32 * 3)(8, 4, 8), 100.0, 3, 320, 256)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return c
+    for kw in ({"voxel_m": 0.0}, {"mu_m": -1.0}, {"w_max": 0.5}, {"max_width": 4},
+               {"blocks": (psweep._i32 * 3)(0, 4, 4)}, {"blocks": (psweep._i32 * 3)(1024, 1024, 1024)}):
+        with pytest.raises(psweep.PsweepError) as ei:
+            psweep.psweep_tsdf_create(cfg(**kw))
+        assert ei.value.status == psweep.EINVAL
+    ts = psweep.psweep_tsdf_create(cfg())
+    assert psweep.psweep_tsdf_workspace_size(ts) >= 8 * 4 * 8 * 4096
+    L = psweep.lib()
+    # integrating before the workspace is bound and the map reset is a state error
+    cam = psweep.psweep_camera(0.9, 100.0, 100.0, 160.0, 128.0, 320, 256)
+    pose = psweep.psweep_pose()
+    c3 = (psweep._d * 3)(0.0, 0.0, 0.0)
+    assert L.psweep_tsdf_integrate(ts, cam, pose, c3, 1, 0, None) == psweep.ESTATE
+    assert L.psweep_tsdf_extract(ts, None, None, None, None) == psweep.ESTATE
+    psweep.psweep_tsdf_destroy(ts)

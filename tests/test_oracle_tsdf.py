@@ -107,7 +107,9 @@ def test_allocation_matches_dense_sampling():
                 sampled[bz, by, bx] = 1
     assert np.all(o.alloc[sampled == 1] == 1)
     extra = (o.alloc == 1) & (sampled == 0)
-    assert np.all(info["pen"][extra] < 2.5 * (2 * MU) / 2000)
+    # a block holding no sample point is met by a piece shorter than the
+    # sample spacing, which cannot reach deeper into it than that spacing
+    assert np.all(info["pen"][extra] < (2 * MU) / 2000)
     assert o.alloc.sum() > 200
 
 
