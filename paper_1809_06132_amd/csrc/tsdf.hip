@@ -123,9 +123,14 @@ __global__ void tsdf_alloc_kernel(TsdfDev T) {
             const int bx = T.b0[0] + cur[0], by = T.b0[1] + cur[1], bz = T.b0[2] + cur[2];
             const int s = slot_of(T, bx, by, bz);
             const unsigned long long key = pack_block(bx, by, bz);
-            const unsigned long long old = atomicCAS(T.keys + s, 0ull, key);
-            if (old == 0ull) T.fresh[s] = 1;
-            T.seen[s] = 1;
+            // most pixels meet blocks that are already allocated and marked:
+            // read first, so that only the first visits contend for the
+            // atomic (the compare-and-swap still decides who allocates)
+            if (__atomic_load_n(T.keys + s, __ATOMIC_RELAXED) != key) {
+                const unsigned long long old = atomicCAS(T.keys + s, 0ull, key);
+                if (old == 0ull) T.fresh[s] = 1;
+            }
+            if (!__atomic_load_n(T.seen + s, __ATOMIC_RELAXED)) T.seen[s] = 1;
         }
         const int ax = tmax[0] <= tmax[1] ? (tmax[0] <= tmax[2] ? 0 : 2) : (tmax[1] <= tmax[2] ? 1 : 2);
         if (tmax[ax] > 1.0f) break;
