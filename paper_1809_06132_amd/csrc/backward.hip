@@ -32,6 +32,15 @@
 
 namespace psw {
 
+// lane l gets v of lane l - 1 (wave_shr:1) or of lane l + 1 (wave_shl:1);
+// the lane with no neighbour gets `fill`
+__device__ __forceinline__ int lane_shr1_i(int v, int fill) {
+    return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int lane_shl1_i(int v, int fill) {
+    return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
+}
+
 __global__ void zero_kernel(float *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0f;
@@ -268,6 +277,12 @@ struct Backward {
                     rA += ch[0]; rB += ch[(size_t)TYO * kWave];
                     rC += ch[(size_t)2 * TYO * kWave]; rE += ch[(size_t)3 * TYO * kWave];
                 }
+                // pose terms of this plane in FP32 (at most RS per lane), then FP64
+                float ps[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                // bottom taps carried down from the previous sample row of this
+                // lane: texel index (-1: none) and value of (v1, i0) and (v1, i1)
+                int ca0 = -1, ca1 = -1;
+                float cv0 = 0.f, cv1 = 0.f;
 #pragma unroll
                 for (int i = 0; i < RS; ++i) {
                     const int j = j0 + i;
@@ -286,52 +301,84 @@ struct Backward {
                     const float sC = wsum<WIN>(rC, sh), sE = wsum<WIN>(rE, sh);
                     const float b = tile[((size_t)s * T + j) * kWave + lane];
                     const float gb = fmaf(aw[i], sA, -sB) + fmaf(-b, sC, sE);
-                    if (gb == 0.0f || is_neg_zero(b)) continue;
-                    // recompute the warp of this sample with its derivatives
-                    const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
-                    const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
-                    const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
-                    const float m = __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z)));
-                    const float den = fmaf(sd.xi, m, Z);
-                    const float inv = __builtin_amdgcn_rcpf(den);
-                    const float u = fmaf(X * inv, sd.fx, sd.cx);
-                    const float v = fmaf(Y * inv, sd.fy, sd.cy);
-                    const int i0 = (int)u, v0 = (int)v;
-                    const int i1 = i0 + 1 < sd.w ? i0 + 1 : sd.w - 1;
-                    const int v1 = v0 + 1 < sd.h ? v0 + 1 : sd.h - 1;
-                    const float al = u - (float)i0, be = v - (float)v0;
-                    const auto q = Texel<IMG>::load(rs, __umul24((uint32_t)v0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes);
-                    const float p00 = q.p00, p10 = q.p10, p01 = q.p01, p11 = q.p11;
-                    if (gimg) {   // image gradient requested for this source
-                        atomicAdd(gimg + (int64_t)v0 * sd.w + i0, gb * (1.0f - al) * (1.0f - be));
-                        atomicAdd(gimg + (int64_t)v0 * sd.w + i1, gb * al * (1.0f - be));
-                        atomicAdd(gimg + (int64_t)v1 * sd.w + i0, gb * (1.0f - al) * be);
-                        atomicAdd(gimg + (int64_t)v1 * sd.w + i1, gb * al * be);
+                    // the four bilinear taps of this sample: texel index (-1:
+                    // none) and gradient, order (v0, i0), (v0, i1), (v1, i0), (v1, i1)
+                    int a00 = -1, a10 = -1, a01 = -1, a11 = -1;
+                    float c00 = 0.f, c10 = 0.f, c01 = 0.f, c11 = 0.f;
+                    if (gb != 0.0f && !is_neg_zero(b)) {
+                        // recompute the warp of this sample with its derivatives
+                        const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
+                        const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
+                        const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
+                        const float m = __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z)));
+                        const float den = fmaf(sd.xi, m, Z);
+                        const float inv = __builtin_amdgcn_rcpf(den);
+                        const float u = fmaf(X * inv, sd.fx, sd.cx);
+                        const float v = fmaf(Y * inv, sd.fy, sd.cy);
+                        const int i0 = (int)u, v0 = (int)v;
+                        const int i1 = i0 + 1 < sd.w ? i0 + 1 : sd.w - 1;
+                        const int v1 = v0 + 1 < sd.h ? v0 + 1 : sd.h - 1;
+                        const float al = u - (float)i0, be = v - (float)v0;
+                        const auto q = Texel<IMG>::load(rs, __umul24((uint32_t)v0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes);
+                        const float p00 = q.p00, p10 = q.p10, p01 = q.p01, p11 = q.p11;
+                        a00 = v0 * sd.w + i0; a10 = v0 * sd.w + i1;
+                        a01 = v1 * sd.w + i0; a11 = v1 * sd.w + i1;
+                        c00 = gb * (1.0f - al) * (1.0f - be); c10 = gb * al * (1.0f - be);
+                        c01 = gb * (1.0f - al) * be; c11 = gb * al * be;
+                        const float dbu = fmaf(be, p11 - p01, (1.0f - be) * (p10 - p00));
+                        const float dbv = fmaf(al, p11 - p10, (1.0f - al) * (p01 - p00));
+                        // (X, Y, Z) = H (x, y, tau) is the source point divided by
+                        // sigma = d / (n . r~) = 1 / (theta * tau) for fronto planes
+                        const float sigma = 1.0f / (theta * tf[i]);
+                        const float im = 1.0f / m;
+                        const float dd0 = sd.xi * X * im, dd1 = sd.xi * Y * im, dd2 = fmaf(sd.xi * Z, im, 1.0f);
+                        const float iu = sd.fx * inv, iv = sd.fy * inv;
+                        const float xu = X * inv, yv = Y * inv;
+                        // d(u, v)/d(point), point = sigma (X, Y, Z)
+                        const float du0 = iu * (1.0f - xu * dd0), du1 = -iu * xu * dd1, du2 = -iu * xu * dd2;
+                        const float dv0 = -iv * yv * dd0, dv1 = iv * (1.0f - yv * dd1), dv2 = -iv * yv * dd2;
+                        const float gs = gb / sigma;
+                        const float g0 = gs * fmaf(dbu, du0, dbv * dv0);
+                        const float g1 = gs * fmaf(dbu, du1, dbv * dv1);
+                        const float g2 = gs * fmaf(dbu, du2, dbv * dv2);
+                        const float P0 = sigma * X, P1 = sigma * Y, P2 = sigma * Z;
+                        ps[0] += g0;
+                        ps[1] += g1;
+                        ps[2] += g2;
+                        ps[3] += P1 * g2 - P2 * g1;
+                        ps[4] += P2 * g0 - P0 * g2;
+                        ps[5] += P0 * g1 - P1 * g0;
                     }
-                    const float dbu = fmaf(be, p11 - p01, (1.0f - be) * (p10 - p00));
-                    const float dbv = fmaf(al, p11 - p10, (1.0f - al) * (p01 - p00));
-                    // (X, Y, Z) = H (x, y, tau) is the source point divided by
-                    // sigma = d / (n . r~) = 1 / (theta * tau) for fronto planes
-                    const float sigma = 1.0f / (theta * tf[i]);
-                    const float im = 1.0f / m;
-                    const float dd0 = sd.xi * X * im, dd1 = sd.xi * Y * im, dd2 = fmaf(sd.xi * Z, im, 1.0f);
-                    const float iu = sd.fx * inv, iv = sd.fy * inv;
-                    const float xu = X * inv, yv = Y * inv;
-                    // d(u, v)/d(point), point = sigma (X, Y, Z)
-                    const float du0 = iu * (1.0f - xu * dd0), du1 = -iu * xu * dd1, du2 = -iu * xu * dd2;
-                    const float dv0 = -iv * yv * dd0, dv1 = iv * (1.0f - yv * dd1), dv2 = -iv * yv * dd2;
-                    const float gs = gb / sigma;
-                    const float g0 = gs * fmaf(dbu, du0, dbv * dv0);
-                    const float g1 = gs * fmaf(dbu, du1, dbv * dv1);
-                    const float g2 = gs * fmaf(dbu, du2, dbv * dv2);
-                    const float P0 = sigma * X, P1 = sigma * Y, P2 = sigma * Z;
-                    acc[s][0] += (double)g0;
-                    acc[s][1] += (double)g1;
-                    acc[s][2] += (double)g2;
-                    acc[s][3] += (double)(P1 * g2 - P2 * g1);
-                    acc[s][4] += (double)(P2 * g0 - P0 * g2);
-                    acc[s][5] += (double)(P0 * g1 - P1 * g0);
+                    if (gimg) {   // image gradient requested for this source
+                        // Neighbouring samples of a near-unit-scale warp share
+                        // taps: fold them together before the atomics.
+                        // (a) this lane's bottom taps of the previous row are
+                        // this row's top taps (same texel row and columns)
+                        if (ca0 >= 0 && ca0 == a00) {
+                            c00 += cv0;
+                            c10 += cv1;   // ca1 is a10 or was handed on (cv1 = 0)
+                        } else {
+                            if (ca0 >= 0) atomicAdd(gimg + ca0, cv0);
+                            if (ca1 >= 0) atomicAdd(gimg + ca1, cv1);
+                        }
+                        // (b) the left lane's right taps are this lane's left
+                        // taps; the left lane then drops them
+                        const int l10 = lane_shr1_i(a10, -1);
+                        const float l10v = shr1(c10), l11v = shr1(c11);
+                        if (a00 >= 0 && l10 == a00) { c00 += l10v; c01 += l11v; }
+                        const bool handed = a10 >= 0 && lane_shl1_i(a00, -1) == a10;
+                        if (a00 >= 0) atomicAdd(gimg + a00, c00);
+                        if (a10 >= 0 && !handed) atomicAdd(gimg + a10, c10);
+                        ca0 = a01; cv0 = c01;
+                        ca1 = handed ? -1 : a11; cv1 = handed ? 0.f : c11;
+                    }
                 }
+                if (gimg) {
+                    if (ca0 >= 0) atomicAdd(gimg + ca0, cv0);
+                    if (ca1 >= 0) atomicAdd(gimg + ca1, cv1);
+                }
+#pragma unroll
+                for (int a = 0; a < 6; ++a) acc[s][a] += (double)ps[a];
             }
             __syncthreads();
         }
