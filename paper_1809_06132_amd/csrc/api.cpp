@@ -24,7 +24,7 @@ extern "C" const void *psw_merge_kernel();
 extern "C" const void *psw_chunk_merge_kernel();
 extern "C" const void *psw_filter_kernel();
 extern "C" const void *psw_mask_kernel();
-extern "C" const void *psw_backward_kernel(int win, int n_src, int img);
+extern "C" const void *psw_backward_kernel(int win, int n_src, int img, int image_grads);
 extern "C" size_t psw_backward_lds(int win, int n_src);
 extern "C" int psw_backward_tile_rows();
 extern "C" const void *psw_zero_kernel();
@@ -906,7 +906,9 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
         PSW_HIP(hipLaunchKernel(zk, dim3(1), dim3(256), a, 0, stream), "zero");
     }
     const int win = ctx->cfg.level[0].window;
-    const void *bk = psw_backward_kernel(win, C.n_src, ctx->cfg.image_format);
+    bool any_image = false;
+    for (int s = 0; s < C.n_src; ++s) any_image |= gsrc[s] != nullptr;
+    const void *bk = psw_backward_kernel(win, C.n_src, ctx->cfg.image_format, any_image ? 1 : 0);
     if (!bk) return fail(ctx, PSWEEP_EUNSUPPORTED, "no backward kernel for this window / source count");
     const size_t lds = psw_backward_lds(win, C.n_src);
     if (lds > 65536) PSW_HIP(hipFuncSetAttribute(bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds limit");

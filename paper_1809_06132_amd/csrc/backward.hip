@@ -41,12 +41,18 @@ __device__ __forceinline__ int lane_shl1_i(int v, int fill) {
     return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
 }
 
+// atomic add of v to the float at byte offset off of a buffer (no return)
+__device__ __forceinline__ void gadd(__amdgpu_buffer_rsrc_t rs, int off, float v) {
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(v, rs, off, 0, 0);
+}
+
 __global__ void zero_kernel(float *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0f;
 }
 
-template <int WIN, int S, int IMG>
+// GI: whether any source's image gradient is wanted (false: pose only)
+template <int WIN, int S, int IMG, bool GI>
 struct Backward {
     static constexpr int NW = 4, R = 4;
     static constexpr int HW = WIN / 2;
@@ -267,7 +273,11 @@ struct Backward {
                 const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                     (void *)sd.tex, (short)0, (int)(row_bytes * (uint32_t)sd.h), 0x00020000);
                 const float px = h1x * x, py = h1y * x, pz = h1z * x;
-                float *gimg = gsrc[s];
+                float *gimg = GI ? gsrc[s] : nullptr;
+                // the gradient image as a buffer: taps are byte offsets into it
+                const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+                    gimg, (short)0, (int)((uint32_t)sd.w * (uint32_t)sd.h * 4u), 0x00020000);
+                const uint32_t grow = (uint32_t)sd.w * 4u;
                 // running sums of the channels over the output rows whose
                 // window holds sample row j: rows [j - 2 HW, j] within the tile
                 const float *chs = chan + ((size_t)s * NCH) * TYO * kWave + lane;
@@ -280,7 +290,7 @@ struct Backward {
                 // pose terms of this plane in FP32 (at most RS per lane), then FP64
                 float ps[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 // bottom taps carried down from the previous sample row of this
-                // lane: texel index (-1: none) and value of (v1, i0) and (v1, i1)
+                // lane: byte offset (-1: none) and value of (v1, i0) and (v1, i1)
                 int ca0 = -1, ca1 = -1;
                 float cv0 = 0.f, cv1 = 0.f;
 #pragma unroll
@@ -301,11 +311,12 @@ struct Backward {
                     const float sC = wsum<WIN>(rC, sh), sE = wsum<WIN>(rE, sh);
                     const float b = tile[((size_t)s * T + j) * kWave + lane];
                     const float gb = fmaf(aw[i], sA, -sB) + fmaf(-b, sC, sE);
-                    // the four bilinear taps of this sample: texel index (-1:
-                    // none) and gradient, order (v0, i0), (v0, i1), (v1, i0), (v1, i1)
+                    // the four bilinear taps of this sample: byte offset of the
+                    // texel in the gradient image (-1: none) and gradient, order
+                    // (v0, i0), (v0, i1), (v1, i0), (v1, i1)
                     int a00 = -1, a10 = -1, a01 = -1, a11 = -1;
                     float c00 = 0.f, c10 = 0.f, c01 = 0.f, c11 = 0.f;
-                    if (gb != 0.0f && !is_neg_zero(b)) {
+                    if ((gb != 0.0f) & !is_neg_zero(b)) {
                         // recompute the warp of this sample with its derivatives
                         const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
                         const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
@@ -321,35 +332,36 @@ struct Backward {
                         const float al = u - (float)i0, be = v - (float)v0;
                         const auto q = Texel<IMG>::load(rs, __umul24((uint32_t)v0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes);
                         const float p00 = q.p00, p10 = q.p10, p01 = q.p01, p11 = q.p11;
-                        a00 = v0 * sd.w + i0; a10 = v0 * sd.w + i1;
-                        a01 = v1 * sd.w + i0; a11 = v1 * sd.w + i1;
+                        a00 = (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i0 * 4u);
+                        a10 = (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i1 * 4u);
+                        a01 = (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i0 * 4u);
+                        a11 = (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i1 * 4u);
                         c00 = gb * (1.0f - al) * (1.0f - be); c10 = gb * al * (1.0f - be);
                         c01 = gb * (1.0f - al) * be; c11 = gb * al * be;
                         const float dbu = fmaf(be, p11 - p01, (1.0f - be) * (p10 - p00));
                         const float dbv = fmaf(al, p11 - p10, (1.0f - al) * (p01 - p00));
-                        // (X, Y, Z) = H (x, y, tau) is the source point divided by
-                        // sigma = d / (n . r~) = 1 / (theta * tau) for fronto planes
-                        const float sigma = 1.0f / (theta * tf[i]);
-                        const float im = 1.0f / m;
-                        const float dd0 = sd.xi * X * im, dd1 = sd.xi * Y * im, dd2 = fmaf(sd.xi * Z, im, 1.0f);
-                        const float iu = sd.fx * inv, iv = sd.fy * inv;
+                        // (X, Y, Z) = H (x, y, tau) is the source point P divided by
+                        // sigma = 1 / (theta tau) (fronto planes).  With
+                        // xu = X / den, yv = Y / den, Au = dbu fx / den,
+                        // Av = dbv fy / den, Q = Au xu + Av yv and
+                        // Qm = xi Q / |(X, Y, Z)|, the sample's gradient along P is
+                        // (gb / sigma) g' with g' = (Au - X Qm, Av - Y Qm, -(Q + Z Qm)),
+                        // so the translation part is gb theta tau g' and the
+                        // rotation part P x (gb / sigma) g' = gb (X, Y, Z) x g'.
                         const float xu = X * inv, yv = Y * inv;
-                        // d(u, v)/d(point), point = sigma (X, Y, Z)
-                        const float du0 = iu * (1.0f - xu * dd0), du1 = -iu * xu * dd1, du2 = -iu * xu * dd2;
-                        const float dv0 = -iv * yv * dd0, dv1 = iv * (1.0f - yv * dd1), dv2 = -iv * yv * dd2;
-                        const float gs = gb / sigma;
-                        const float g0 = gs * fmaf(dbu, du0, dbv * dv0);
-                        const float g1 = gs * fmaf(dbu, du1, dbv * dv1);
-                        const float g2 = gs * fmaf(dbu, du2, dbv * dv2);
-                        const float P0 = sigma * X, P1 = sigma * Y, P2 = sigma * Z;
-                        ps[0] += g0;
-                        ps[1] += g1;
-                        ps[2] += g2;
-                        ps[3] += P1 * g2 - P2 * g1;
-                        ps[4] += P2 * g0 - P0 * g2;
-                        ps[5] += P0 * g1 - P1 * g0;
+                        const float Au = dbu * (sd.fx * inv), Av = dbv * (sd.fy * inv);
+                        const float Q = fmaf(Au, xu, Av * yv);
+                        const float Qm = Q * (sd.xi * __builtin_amdgcn_rcpf(m));
+                        const float e0 = fmaf(-X, Qm, Au), e1 = fmaf(-Y, Qm, Av), e2 = -fmaf(Z, Qm, Q);
+                        const float gt = gb * tf[i];   // times theta once per plane
+                        ps[0] = fmaf(gt, e0, ps[0]);
+                        ps[1] = fmaf(gt, e1, ps[1]);
+                        ps[2] = fmaf(gt, e2, ps[2]);
+                        ps[3] = fmaf(gb, fmaf(Y, e2, -Z * e1), ps[3]);
+                        ps[4] = fmaf(gb, fmaf(Z, e0, -X * e2), ps[4]);
+                        ps[5] = fmaf(gb, fmaf(X, e1, -Y * e0), ps[5]);
                     }
-                    if (gimg) {   // image gradient requested for this source
+                    if (GI && gimg) {   // image gradient requested for this source
                         // Neighbouring samples of a near-unit-scale warp share
                         // taps: fold them together before the atomics.
                         // (a) this lane's bottom taps of the previous row are
@@ -358,8 +370,8 @@ struct Backward {
                             c00 += cv0;
                             c10 += cv1;   // ca1 is a10 or was handed on (cv1 = 0)
                         } else {
-                            if (ca0 >= 0) atomicAdd(gimg + ca0, cv0);
-                            if (ca1 >= 0) atomicAdd(gimg + ca1, cv1);
+                            if (ca0 >= 0) gadd(grs, ca0, cv0);
+                            if (ca1 >= 0) gadd(grs, ca1, cv1);
                         }
                         // (b) the left lane's right taps are this lane's left
                         // taps; the left lane then drops them
@@ -367,18 +379,20 @@ struct Backward {
                         const float l10v = shr1(c10), l11v = shr1(c11);
                         if (a00 >= 0 && l10 == a00) { c00 += l10v; c01 += l11v; }
                         const bool handed = a10 >= 0 && lane_shl1_i(a00, -1) == a10;
-                        if (a00 >= 0) atomicAdd(gimg + a00, c00);
-                        if (a10 >= 0 && !handed) atomicAdd(gimg + a10, c10);
+                        if (a00 >= 0) gadd(grs, a00, c00);
+                        if (a10 >= 0 && !handed) gadd(grs, a10, c10);
                         ca0 = a01; cv0 = c01;
                         ca1 = handed ? -1 : a11; cv1 = handed ? 0.f : c11;
                     }
                 }
-                if (gimg) {
-                    if (ca0 >= 0) atomicAdd(gimg + ca0, cv0);
-                    if (ca1 >= 0) atomicAdd(gimg + ca1, cv1);
+                if (GI && gimg) {
+                    if (ca0 >= 0) gadd(grs, ca0, cv0);
+                    if (ca1 >= 0) gadd(grs, ca1, cv1);
                 }
 #pragma unroll
-                for (int a = 0; a < 6; ++a) acc[s][a] += (double)ps[a];
+                for (int a = 0; a < 3; ++a) acc[s][a] += (double)(ps[a] * theta);
+#pragma unroll
+                for (int a = 3; a < 6; ++a) acc[s][a] += (double)ps[a];
             }
             __syncthreads();
         }
@@ -390,19 +404,19 @@ struct Backward {
                 double v = acc[s][a];
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-                if (lane == 0 && v != 0.0) atomicAdd(gpose + s * 6 + a, v);
+                if (lane == 0 && v != 0.0) unsafeAtomicAdd(gpose + s * 6 + a, v);   // device memory: hardware FP64 add
             }
     }
 };
 
-template <int WIN, int S, int IMG>
+template <int WIN, int S, int IMG, bool GI>
 __global__ __launch_bounds__(256) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
                                                         const float *__restrict__ rho, const float *__restrict__ lse,
                                                         int64_t spitch, float *g0, float *g1, float *g2, float *g3,
                                                         double *gpose) {
     extern __shared__ char smem[];
     float *gs[4] = {g0, g1, g2, g3};
-    Backward<WIN, S, IMG>::run(job, gin, rho, lse, spitch, gs, gpose, smem);
+    Backward<WIN, S, IMG, GI>::run(job, gin, rho, lse, spitch, gs, gpose, smem);
 }
 
 }  // namespace psw
@@ -410,26 +424,28 @@ __global__ __launch_bounds__(256) void backward_kernel(const JobDev *__restrict_
 extern "C" {
 const void *psw_zero_kernel() { return (const void *)&psw::zero_kernel; }
 
-const void *psw_backward_kernel(int win, int n_src, int img) {
-#define PSW_B(W, I)                                                                      \
-    if (win == W && img == I) {                                                          \
-        if (n_src == 1) return (const void *)&psw::backward_kernel<W, 1, I>;            \
-        if (n_src == 2) return (const void *)&psw::backward_kernel<W, 2, I>;            \
-        if (n_src == 3) return (const void *)&psw::backward_kernel<W, 3, I>;            \
+const void *psw_backward_kernel(int win, int n_src, int img, int image_grads) {
+#define PSW_B(W, I, G)                                                                   \
+    if (win == W && img == I && (image_grads != 0) == G) {                               \
+        if (n_src == 1) return (const void *)&psw::backward_kernel<W, 1, I, G>;         \
+        if (n_src == 2) return (const void *)&psw::backward_kernel<W, 2, I, G>;         \
+        if (n_src == 3) return (const void *)&psw::backward_kernel<W, 3, I, G>;         \
     }
-    PSW_B(5, 0) PSW_B(7, 0) PSW_B(9, 0) PSW_B(5, 1) PSW_B(7, 1) PSW_B(9, 1)
+    PSW_B(5, 0, true) PSW_B(7, 0, true) PSW_B(9, 0, true) PSW_B(5, 1, true) PSW_B(7, 1, true) PSW_B(9, 1, true)
+    PSW_B(5, 0, false) PSW_B(7, 0, false) PSW_B(9, 0, false) PSW_B(5, 1, false) PSW_B(7, 1, false)
+    PSW_B(9, 1, false)
 #undef PSW_B
     return nullptr;
 }
 
-int psw_backward_tile_rows() { return psw::Backward<5, 1, 0>::TYO; }
+int psw_backward_tile_rows() { return psw::Backward<5, 1, 0, true>::TYO; }
 
 size_t psw_backward_lds(int win, int n_src) {
 #define PSW_L(W)                                                       \
     if (win == W) {                                                    \
-        if (n_src == 1) return psw::Backward<W, 1, 0>::lds_bytes();    \
-        if (n_src == 2) return psw::Backward<W, 2, 0>::lds_bytes();    \
-        if (n_src == 3) return psw::Backward<W, 3, 0>::lds_bytes();    \
+        if (n_src == 1) return psw::Backward<W, 1, 0, true>::lds_bytes();    \
+        if (n_src == 2) return psw::Backward<W, 2, 0, true>::lds_bytes();    \
+        if (n_src == 3) return psw::Backward<W, 3, 0, true>::lds_bytes();    \
     }
     PSW_L(5) PSW_L(7) PSW_L(9)
 #undef PSW_L
