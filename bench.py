@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "plane-pixel evals/s (Gpix·planes/s) + depth maps/s vs plain FP32, 1 GPU"
 # non-packed FP32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8e12   # bytes/s
 
 
 def algorithmic_ops_per_plane_pixel(n_src: int) -> int:
@@ -67,7 +68,10 @@ def counted_traffic():
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
 
-def cpu_baseline(fr, st, target_s=15.0):
+def cpu_baseline(fr, st, target_s=15.0, one_core_s=5.0):
+    """The FP64 oracle on random pixels of the frame (every plane and source of
+    each): median of three runs of about target_s / 3 seconds on all the
+    oracle's threads, and one run of about one_core_s on a single thread."""
     import numpy as np
 
     import oracle
@@ -78,18 +82,30 @@ def cpu_baseline(fr, st, target_s=15.0):
     def sample(n):
         return np.stack([rng.integers(0, fr.ref.shape[1], n), rng.integers(0, fr.ref.shape[0], n)], 1).astype(np.int32)
 
-    n = 1024
-    t0 = time.perf_counter()
-    oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=sample(n))
-    dt = time.perf_counter() - t0
-    n2 = int(min(2_000_000, max(1024, n * (target_s - dt) / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=sample(n2))
-    dt2 = time.perf_counter() - t0
+    def timed(n):
+        px = sample(n)
+        t0 = time.perf_counter()
+        oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=px)
+        return time.perf_counter() - t0
+
+    def sized(seconds, probe=1024):
+        dt = timed(probe)
+        return int(min(2_000_000, max(probe, probe * seconds / max(dt, 1e-3))))
+
     cores = oracle.threads()
-    return {"value": n2 * P / dt2 / 1e9, "unit": "Gpix·planes/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n2} random pixels of the 1024x768 frame, all {P} planes x 3 sources, "
-                      f"FP64 two-pass ZNCC per window ({dt2:.1f} s)"}
+    n = sized(target_s / 3)
+    runs = sorted(timed(n) for _ in range(3))
+    dt = runs[1]
+    oracle.set_threads(1)
+    try:
+        n1 = sized(one_core_s, probe=256)
+        dt1 = timed(n1)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": n * P / dt / 1e9, "unit": "Gpix·planes/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} random pixels of the 1024x768 frame, all {P} planes x 3 sources, FP64 two-pass "
+                      f"ZNCC per window; median of 3 runs ({', '.join(f'{t:.1f}' for t in runs)} s)",
+            "one_core": {"value": n1 * P / dt1 / 1e9, "cores": 1, "sample": f"{n1} random pixels, {dt1:.1f} s"}}
 
 
 def bench_c5(args):
@@ -412,6 +428,11 @@ def main():
     ops = plane_pixels * algorithmic_ops_per_plane_pixel(len(fr.srcs))
     achieved = ops / (kernel_ms * 1e-3) / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    traffic = counted_traffic()
+    # algorithmic HBM bytes of one map: the 8-bit reference and sources once,
+    # and 24 B of outputs per pixel (index, offset, two costs, range, z)
+    W, H = fr.ref_cam.width, fr.ref_cam.height
+    alg_bytes = float((1 + len(fr.srcs)) * W * H + 24 * W * H)
     line = {
         "metric": METRIC,
         "value": plane_pixels / (ms * 1e-3) / 1e9,
@@ -431,9 +452,13 @@ def main():
                                "ZNCC 9x9, mean of best 2, WTA + parabola",
                    "plane_pixels_per_step": plane_pixels, "launch": "grid", "storage": args.storage},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-ops/s",
-                     "frac": achieved / peak, "traffic": counted_traffic(),
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel_ms": kernel_ms,
-                     "ops_per_plane_pixel": algorithmic_ops_per_plane_pixel(len(fr.srcs))},
+                     "ops_per_plane_pixel": algorithmic_ops_per_plane_pixel(len(fr.srcs)),
+                     # not binding: the HBM side of the same launch, as fractions of 8 TB/s
+                     "hbm": {"algorithmic_bytes": alg_bytes,
+                             "algorithmic_frac": alg_bytes / (kernel_ms * 1e-3) / HBM_PEAK,
+                             "counted_frac": None if traffic is None else traffic / (kernel_ms * 1e-3) / HBM_PEAK}},
     }
     ps.close()
     if args.copy_calibration:

@@ -99,6 +99,8 @@ def lib():
     L.or_filter.restype = None
     L.or_threads.argtypes = []
     L.or_threads.restype = _i32
+    L.or_set_threads.argtypes = [_i32]
+    L.or_set_threads.restype = None
     L.or_tsdf_alloc.argtypes = [PC, PP, _p, _i64, _d, _d, _p, _p, _p, _p]
     L.or_tsdf_alloc.restype = None
     L.or_tsdf_visible.argtypes = [PC, PP, _d, _p, _p, _p, _p, _p]
@@ -413,6 +415,11 @@ def depth_filter(cam, ground_n, depth, cost1, cost2, alpha_upper=0.05, alpha_low
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count of the oracle's parallel loops."""
+    lib().or_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------

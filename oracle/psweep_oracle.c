@@ -669,3 +669,6 @@ void or_filter(const or_camera *cam, const double ground_n[3], int32_t w, int32_
 
 /* Threads the parallel loops above use (for reporting the baseline's cores). */
 int or_threads(void) { return omp_get_max_threads(); }
+
+/* Set that thread count (n >= 1) for the calling thread's later loops. */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
