@@ -26,9 +26,9 @@
  *     are x = (u - cx) / fx, y = (v - cy) / fy.
  *   - Reference frame: x right, y down, z forward, metres.  A source sees
  *     X_src = R X_ref + t (R row-major).
- *   - Images are 8-bit grey, row-major, in device memory, with a row pitch in
- *     bytes.  Output maps are row-major device arrays with a pitch in
- *     elements.
+ *   - Images are 8-bit grey (or float, PSWEEP_IMAGE_F32), row-major, in
+ *     device memory, with a row pitch in elements (pixels).  Output maps are
+ *     row-major device arrays with a pitch in elements.
  *   - All device memory (images, outputs, workspace) is owned by the caller.
  *     The context owns host-side state only.
  *   - Every call returns a psweep_status and never aborts.  Launch errors are
@@ -36,7 +36,9 @@
  *     undefined after an error.  psweep_last_error() gives a message.
  *   - Work is enqueued asynchronously on the caller's HIP stream; only
  *     psweep_destroy() synchronises.  A context must not be used from two
- *     host threads at once.
+ *     host threads at once.  Successive runs of one context reuse its
+ *     workspace (job tables, level images, partial states): enqueue them on
+ *     one stream, or order them with events.  Contexts are independent.
  *   - Invalid pixels are marked in-band: depth and z NaN, index -1, delta 0,
  *     cost1 and cost2 +inf, level 255.
  */

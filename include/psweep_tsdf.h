@@ -45,8 +45,9 @@ typedef struct {
     int32_t max_width, max_height;  /* largest depth map */
 } psweep_tsdf_config;
 
-/* Create a map.  EINVAL for non-positive sizes, blocks out of [1, 1024], a
- * box of more than 2^24 blocks, w_max < 1 or max sizes out of [8, 8192]. */
+/* Create a map.  EINVAL for non-positive sizes, mu_m above 16 blocks
+ * (128 voxel_m), blocks out of [1, 1024], a box of more than 2^24 blocks,
+ * w_max < 1 or max sizes out of [8, 8192]. */
 psweep_status psweep_tsdf_create(const psweep_tsdf_config *cfg, psweep_tsdf **out);
 
 /* Bytes of device workspace the map needs (fixed by the config: 8 bytes per
@@ -67,8 +68,9 @@ psweep_status psweep_tsdf_reset(psweep_tsdf *ts, void *hip_stream);
  * (R_d, t_d)); centre: world point the box is centred on (block b0 = floor(c
  * / B) - blocks / 2 per axis); depth: device float range along the Eq. (1)
  * ray in metres (NaN or <= 0: invalid), row pitch in elements (0 = width).
- * Asynchronous.  EINVAL for NULL arguments or sizes above the maximum; ESTATE
- * before workspace and reset. */
+ * Asynchronous.  EINVAL for NULL arguments, sizes above the maximum, a
+ * non-finite camera or pose, a rotation that is not orthonormal, or a centre
+ * whose block coordinates leave +-2^20; ESTATE before workspace and reset. */
 psweep_status psweep_tsdf_integrate(psweep_tsdf *ts, const psweep_camera *cam, const psweep_pose *world_to_cam,
                                     const double centre[3], const float *depth, int64_t pitch, void *hip_stream);
 

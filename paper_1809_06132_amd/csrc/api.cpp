@@ -67,34 +67,26 @@ LevelCam level_cam(const psweep_camera &c, int ds, int cx0, int cy0, int cw, int
     return o;
 }
 
-const KernelEntry *g_entries = nullptr;
-int g_n_entries = 0;
-std::vector<KernelEntry> g_all;
-
-void load_tables() {
-    if (!g_all.empty()) return;
-    const KernelEntry *t;
-    int n = psw_kernels_grid(&t);
-    g_all.insert(g_all.end(), t, t + n);
-    n = psw_kernels_extra(&t);
-    g_all.insert(g_all.end(), t, t + n);
-    n = psw_kernels_small(&t);
-    g_all.insert(g_all.end(), t, t + n);
-    n = psw_kernels_grid8(&t);
-    g_all.insert(g_all.end(), t, t + n);
-    n = psw_kernels_f32img(&t);
-    g_all.insert(g_all.end(), t, t + n);
-    n = psw_kernels_persistent(&t);
-    g_all.insert(g_all.end(), t, t + n);
-    g_entries = g_all.data();
-    g_n_entries = (int)g_all.size();
+// every kernel instance of the library, gathered once (thread-safe static
+// initialisation)
+const std::vector<KernelEntry> &all_kernels() {
+    static const std::vector<KernelEntry> all = [] {
+        std::vector<KernelEntry> v;
+        int (*const tables[])(const KernelEntry **) = {psw_kernels_grid, psw_kernels_extra, psw_kernels_small,
+                                                      psw_kernels_grid8, psw_kernels_f32img, psw_kernels_persistent};
+        for (auto tab : tables) {
+            const KernelEntry *t;
+            const int n = tab(&t);
+            v.insert(v.end(), t, t + n);
+        }
+        return v;
+    }();
+    return all;
 }
 
 const KernelEntry *find_kernel(int win, int rows, int waves, int n_src, int store, int soft, int persistent,
                                int img) {
-    load_tables();
-    for (int i = 0; i < g_n_entries; ++i) {
-        const KernelEntry &e = g_entries[i];
+    for (const KernelEntry &e : all_kernels()) {
         if (e.persistent == persistent && e.rows == rows && e.waves == waves && e.n_src == n_src &&
             e.store == store && e.soft == soft && e.img == img && (persistent || e.win == win))
             return &e;
@@ -201,7 +193,8 @@ psweep_status check_config(const psweep_config *c) {
             if (!(std::fabs(gn - 1.0) < 1e-6)) return bad("ground_n must be a unit vector");
             if (!(c->ground_d - L.h_hi > 0.0)) return bad("ground planes must stay below the camera (ground_d > h_hi)");
         }
-        if (L.crop_w < 0 || L.crop_h < 0 || (L.crop_w > 0 && (L.crop_x < 0 || L.crop_y < 0)))
+        if (L.crop_w < 0 || L.crop_h < 0 || (L.crop_w > 0) != (L.crop_h > 0) ||
+            (L.crop_w > 0 && (L.crop_x < 0 || L.crop_y < 0)))
             return bad("bad crop rectangle");
     }
     if (c->n_levels == 2) {
@@ -302,11 +295,9 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
             ctx->n_cu = prop.multiProcessorCount;
     }
-    load_tables();
     // kernels with more than 64 KB of dynamic LDS need the limit raised
-    for (int i = 0; i < g_n_entries; ++i)
-        if (g_entries[i].lds > 65536)
-            (void)hipFuncSetAttribute(g_entries[i].fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g_entries[i].lds);
+    for (const KernelEntry &e : all_kernels())
+        if (e.lds > 65536) (void)hipFuncSetAttribute(e.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)e.lds);
     *out = ctx;
     return PSWEEP_OK;
 }
@@ -344,12 +335,15 @@ psweep_status psweep_set_cameras(psweep_ctx *ctx, int32_t camera_set, const pswe
     if (!cam_ok(*ref)) return fail(ctx, PSWEEP_EINVAL, "bad reference camera (xi in [0,1], f > 0, size <= max)");
     for (int s = 0; s < n_src; ++s) {
         if (!cam_ok(src[s])) return fail(ctx, PSWEEP_EINVAL, "bad source camera");
+        const double *t = ref_to_src[s].t;
+        if (!(std::isfinite(t[0]) && std::isfinite(t[1]) && std::isfinite(t[2])))
+            return fail(ctx, PSWEEP_EINVAL, "pose translation not finite");
         const double *R = ref_to_src[s].R;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
                 double d = 0;
                 for (int k = 0; k < 3; ++k) d += R[3 * a + k] * R[3 * b + k];
-                if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-6) return fail(ctx, PSWEEP_EINVAL, "R not orthonormal");
+                if (!(std::fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-6)) return fail(ctx, PSWEEP_EINVAL, "R not orthonormal");
             }
     }
     CamSet &cs = ctx->sets[camera_set];
@@ -421,10 +415,10 @@ psweep_status psweep_plane_pixels(const psweep_ctx *ctx, const psweep_frame *fra
 
 namespace {
 
-// Build the per-run tables (host side) for `frames`, with device addresses
-// of the table region `tbase`.
+// Build the per-run tables (host side) for `frames`: job, setup, prep,
+// border and merge records packed at fixed offsets of one blob.
 psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, const psweep_output *out,
-                           char *tbase, Blob &blob, std::vector<int> &job_frame) {
+                           Blob &blob, std::vector<int> &job_frame) {
     const psweep_config &cfg = ctx->cfg;
     const int NL = cfg.n_levels;
     const bool sf = single_full(cfg);
@@ -451,7 +445,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             crop_x = cfg.level[1].crop_x; crop_y = cfg.level[1].crop_y;
             crop_w = cfg.level[1].crop_w; crop_h = cfg.level[1].crop_h;
             if (C.crop_set) { crop_x = C.crop[0]; crop_y = C.crop[1]; crop_w = C.crop[2]; crop_h = C.crop[3]; }
-            if (crop_w <= 0 || crop_x + crop_w > C.ref.width || crop_y + crop_h > C.ref.height)
+            if (crop_w <= 0 || crop_h <= 0 || crop_x + crop_w > C.ref.width || crop_y + crop_h > C.ref.height)
                 return fail(ctx, PSWEEP_EINVAL, "crop rectangle outside the reference image");
         }
         if (sf) {
@@ -575,7 +569,6 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             Sd.n_src = C.n_src; Sd.n_fronto = L.n_fronto; Sd.n_ground = L.n_ground;
             Sd.htab = (float *)(slot + ctx->s_htab[l]);
             Sd.theta = (float *)(slot + ctx->s_theta[l]);
-            (void)P;
             // level images
             PrepDev Pd;
             std::memset(&Pd, 0, sizeof Pd);
@@ -648,7 +641,6 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
     std::memcpy(blob.bytes.data() + blob.preps, preps.data(), sizeof(PrepDev) * nj);
     std::memcpy(blob.bytes.data() + blob.borders, borders.data(), sizeof(BorderDev) * nj);
     if (nm) std::memcpy(blob.bytes.data() + blob.merges, merges.data(), sizeof(MergeDev) * nm);
-    (void)tbase;
     return PSWEEP_OK;
 }
 
@@ -769,7 +761,7 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
     Blob blob;
     std::vector<int> job_frame;
     char *tb = ctx->ws + ctx->off_table[0];
-    psweep_status st = build_tables(ctx, frames, n_frames, out, tb, blob, job_frame);
+    psweep_status st = build_tables(ctx, frames, n_frames, out, blob, job_frame);
     if (st != PSWEEP_OK) return st;
     std::vector<JobDev> hj(blob.nj);
     std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);
@@ -853,7 +845,7 @@ psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, 
     Blob blob;
     std::vector<int> job_frame;
     char *tb = ctx->ws + ctx->off_table[1];
-    psweep_status st = build_tables(ctx, frames, n_frames, out, tb, blob, job_frame);
+    psweep_status st = build_tables(ctx, frames, n_frames, out, blob, job_frame);
     if (st != PSWEEP_OK) return st;
     std::vector<JobDev> hj(blob.nj);
     std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);

@@ -93,6 +93,9 @@ psweep_status psweep_tsdf_create(const psweep_tsdf_config *cfg, psweep_tsdf **ou
     if (!cfg || !out) return tfail(ts, PSWEEP_EINVAL, "NULL argument");
     *out = nullptr;
     if (!(cfg->voxel_m > 0.0) || !(cfg->mu_m > 0.0)) return tfail(ts, PSWEEP_EINVAL, "voxel_m and mu_m must be > 0");
+    // the allocation walks at most 64 blocks per pixel: a segment of 2 mu
+    // crosses at most 2 sqrt(3) mu / B + 3 block faces
+    if (!(cfg->mu_m <= 16.0 * 8.0 * cfg->voxel_m)) return tfail(ts, PSWEEP_EINVAL, "mu_m above 16 blocks");
     long long n = 1;
     for (int a = 0; a < 3; ++a) {
         if (cfg->blocks[a] < 1 || cfg->blocks[a] > 1024) return tfail(ts, PSWEEP_EINVAL, "blocks out of [1, 1024]");
@@ -155,15 +158,28 @@ psweep_status psweep_tsdf_integrate(psweep_tsdf *ts, const psweep_camera *cam, c
                                     const double centre[3], const float *depth, int64_t pitch, void *hip_stream) {
     if (!ts) return PSWEEP_EINVAL;
     if (!cam || !pose || !centre || !depth) return tfail(ts, PSWEEP_EINVAL, "NULL argument");
-    if (!ts->ws || !ts->reset_done) return tfail(ts, PSWEEP_ESTATE, "workspace not set or map never reset");
     if (cam->width < 1 || cam->height < 1 || cam->width > ts->cfg.max_width || cam->height > ts->cfg.max_height)
         return tfail(ts, PSWEEP_EINVAL, "depth map size out of range");
-    if (!(cam->fx > 0.0) || !(cam->fy > 0.0) || !(cam->xi >= 0.0 && cam->xi <= 1.0))
+    if (!(cam->fx > 0.0) || !(cam->fy > 0.0) || !(cam->xi >= 0.0 && cam->xi <= 1.0) || !std::isfinite(cam->cx) ||
+        !std::isfinite(cam->cy))
         return tfail(ts, PSWEEP_EINVAL, "bad camera");
+    for (int i = 0; i < 3; ++i) {
+        if (!std::isfinite(pose->t[i])) return tfail(ts, PSWEEP_EINVAL, "pose translation not finite");
+        for (int j = 0; j < 3; ++j) {
+            double d = 0.0;
+            for (int k = 0; k < 3; ++k) d += pose->R[3 * i + k] * pose->R[3 * j + k];
+            if (!(std::fabs(d - (i == j ? 1.0 : 0.0)) <= 1e-6)) return tfail(ts, PSWEEP_EINVAL, "R not orthonormal");
+        }
+    }
     if (pitch != 0 && pitch < cam->width) return tfail(ts, PSWEEP_EINVAL, "pitch below width");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(centre[a]) || std::fabs(centre[a]) > 1e6) return tfail(ts, PSWEEP_EINVAL, "bad centre");
     const double B = 8.0 * ts->cfg.voxel_m;
+    // block coordinates are packed in 21 bits each, biased by 2^20
+    for (int a = 0; a < 3; ++a)
+        if (!(std::fabs(std::floor(centre[a] / B)) + ts->cfg.blocks[a] < (double)(1 << 20) - 2))
+            return tfail(ts, PSWEEP_EINVAL, "centre too far from the origin for the voxel size");
+    if (!ts->ws || !ts->reset_done) return tfail(ts, PSWEEP_ESTATE, "workspace not set or map never reset");
     for (int a = 0; a < 3; ++a) ts->b0[a] = (int32_t)std::floor(centre[a] / B) - ts->cfg.blocks[a] / 2;
     TsdfDev T = base_dev(ts);
     T.fx = (float)cam->fx; T.fy = (float)cam->fy; T.cx = (float)cam->cx; T.cy = (float)cam->cy;

@@ -79,6 +79,7 @@ class PlaneSweep:
         aligned = (base + 255) // 256 * 256
         P.psweep_set_workspace(self.ctx, aligned, n)
         self.cams = {}
+        self.crops = {}
         self._keep = []
 
     def close(self):
@@ -100,6 +101,7 @@ class PlaneSweep:
 
     def set_crop(self, camera_set, x, y, w, h):
         P.psweep_set_crop(self.ctx, camera_set, x, y, w, h)
+        self.crops[camera_set] = (x, y, w, h)
 
     def set_tile(self, level, rows_per_wave, waves):
         P.psweep_set_tile(self.ctx, level, rows_per_wave, waves)
@@ -128,7 +130,9 @@ class PlaneSweep:
         ref, _ = self.cams[camera_set]
         lv = self.settings.levels[lv_index]
         w, h = ref.width // lv.downsample, ref.height // lv.downsample
-        if lv.crop[2] > 0:
+        if lv_index == 1 and camera_set in self.crops:
+            w, h = self.crops[camera_set][2:]
+        elif lv.crop[2] > 0:
             w, h = lv.crop[2], lv.crop[3]
         return h, w
 
@@ -145,38 +149,60 @@ class PlaneSweep:
 
     # -- marshalling --------------------------------------------------------
     @staticmethod
-    def _maps(m: dict | None) -> P.psweep_maps:
+    def _maps(m: dict | None, shape=None) -> P.psweep_maps:
+        """Map pointers (pitch = width); `shape` (h, w): the size every map
+        must have."""
         pm = P.psweep_maps()
         if m is None:
             return pm
         for key in ("depth", "z", "index", "delta", "cost1", "cost2", "level"):
             t = m.get(key)
             if t is not None:
-                assert t.is_cuda and t.is_contiguous()
+                if not (t.is_cuda and t.is_contiguous() and t.dim() == 2):
+                    raise ValueError(f"map '{key}' must be a contiguous 2-D CUDA tensor")
+                if shape is not None and tuple(t.shape) != tuple(shape):
+                    raise ValueError(f"map '{key}' has shape {tuple(t.shape)}, expected {tuple(shape)}")
                 setattr(pm, key, t.data_ptr())
         pm.pitch = 0
         return pm
 
     def _frame(self, fr: dict) -> P.psweep_frame:
+        """Frame pointers, after checking every image against the size its
+        camera set gives it (the library reads width x height pixels)."""
         f = P.psweep_frame()
-        ref = fr["ref"]
+        f.camera_set = cs = int(fr.get("camera_set", 0))
+        if cs not in self.cams:
+            raise ValueError(f"camera set {cs} has no cameras")
+        ref_cam, src_cams = self.cams[cs]
         dt = self.image_dtype
-        if ref.dtype != dt or ref.device.type != "cuda" or ref.dim() != 2 or ref.stride(1) != 1:
-            raise ValueError(f"reference must be a 2-D row-major {dt} CUDA tensor")
-        f.ref, f.ref_pitch = ref.data_ptr(), ref.stride(0)
-        for s, img in enumerate(fr["srcs"]):
+
+        def check(img, cam, what):
             if img.dtype != dt or img.device.type != "cuda" or img.dim() != 2 or img.stride(1) != 1:
-                raise ValueError(f"source {s} must be a 2-D row-major {dt} CUDA tensor")
-            f.src[s], f.src_pitch[s] = img.data_ptr(), img.stride(0)
-        f.camera_set = int(fr.get("camera_set", 0))
+                raise ValueError(f"{what} must be a 2-D row-major {dt} CUDA tensor")
+            if img.shape[0] < cam.height or img.shape[1] < cam.width:
+                raise ValueError(f"{what} is {tuple(img.shape)}, smaller than its camera "
+                                 f"({cam.height}, {cam.width})")
+            return img.data_ptr(), img.stride(0)
+
+        f.ref, f.ref_pitch = check(fr["ref"], ref_cam, "reference")
+        if len(fr["srcs"]) != len(src_cams):
+            raise ValueError(f"{len(fr['srcs'])} source images for {len(src_cams)} source cameras")
+        for s, img in enumerate(fr["srcs"]):
+            f.src[s], f.src_pitch[s] = check(img, src_cams[s], f"source {s}")
         return f
 
-    def _output(self, o: dict) -> P.psweep_output:
+    def _output(self, o: dict, camera_set: int) -> P.psweep_output:
+        ref, _ = self.cams[camera_set]
+        full = (ref.height, ref.width)
         po = P.psweep_output()
-        po.merged = self._maps(o.get("merged"))
+        po.merged = self._maps(o.get("merged"), full)
         for l, m in enumerate(o.get("levels", []) or []):
-            po.level[l] = self._maps(m)
+            po.level[l] = self._maps(m, self.level_size(camera_set, l))
         if "soft_invdepth" in o:
+            for key in ("soft_invdepth", "soft_lse"):
+                t = o[key]
+                if not (t.is_cuda and t.is_contiguous() and tuple(t.shape) == full and t.dtype == torch.float32):
+                    raise ValueError(f"'{key}' must be a contiguous float32 CUDA tensor of shape {full}")
             po.soft_invdepth = o["soft_invdepth"].data_ptr()
             po.soft_lse = o["soft_lse"].data_ptr()
         return po
@@ -186,17 +212,22 @@ class PlaneSweep:
         """Enqueue one run of the whole sweep for `frames` (list of dicts with
         'ref', 'srcs', 'camera_set') into `outputs` (list of dicts from
         alloc_outputs)."""
+        if len(frames) != len(outputs):
+            raise ValueError("one output per frame")
         pf = [self._frame(f) for f in frames]
-        po = [self._output(o) for o in outputs]
+        po = [self._output(o, f.camera_set) for o, f in zip(outputs, pf)]
         P.psweep_run(self.ctx, pf, po, _stream_handle(stream))
         if self.settings.mode == "soft":
             # the backward re-reads the reference image of this run: hold the
             # tensors so the caching allocator cannot hand their memory out
             self._soft_frames = list(frames)
+            self._soft_shape = tuple(outputs[0]["soft_invdepth"].shape)
 
     def capture_graph(self, frames, outputs, stream=None):
+        if len(frames) != len(outputs):
+            raise ValueError("one output per frame")
         pf = [self._frame(f) for f in frames]
-        po = [self._output(o) for o in outputs]
+        po = [self._output(o, f.camera_set) for o, f in zip(outputs, pf)]
         self._keep = [frames, outputs]
         P.psweep_graph_capture(self.ctx, pf, po, _stream_handle(stream))
 
@@ -212,8 +243,8 @@ class PlaneSweep:
         c = torch.empty((ref.height, ref.width), dtype=torch.uint8, device=self.device)
         prm = P.psweep_filter_params(float(alpha_upper), float(alpha_lower), float(ratio_min), float(gamma),
                                      float(delta), int(window))
-        P.psweep_filter(self.ctx, camera_set, self._maps(merged), prm, d.data_ptr(), c.data_ptr(), 0,
-                        _stream_handle(stream))
+        P.psweep_filter(self.ctx, camera_set, self._maps(merged, (ref.height, ref.width)), prm, d.data_ptr(),
+                        c.data_ptr(), 0, _stream_handle(stream))
         return d, c
 
     def mask_boxes(self, depth, boxes, code=None, camera_set=0, stream=None):
@@ -233,7 +264,11 @@ class PlaneSweep:
         per-source image gradients (None where not requested) and a [S, 6]
         float64 pose gradient (v, omega).  image_grads: True, False, or one
         flag per source."""
+        if tuple(grad_invdepth.shape) != getattr(self, "_soft_shape", None):
+            raise ValueError("the gradient must have the shape of the last soft run's output")
         g = grad_invdepth.contiguous().float()
+        if stream is not None and g is not grad_invdepth:
+            g.record_stream(stream)   # a temporary read on another stream
         want = [image_grads] * len(src_shapes) if isinstance(image_grads, bool) else list(image_grads)
         gs = [torch.empty(s, dtype=torch.float32, device=self.device) if w else None
               for s, w in zip(src_shapes, want)]

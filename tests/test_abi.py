@@ -68,6 +68,7 @@ def _cfg(psweep, **kw):
     ({"mode": 1, "launch": 1}, -5),
     ({"launch": 1, "0.window": 5}, -5),
     ({"0.crop_w": 100, "0.crop_h": 100}, -5),
+    ({"0.crop_w": 100, "0.crop_h": 0}, -1),                                 # crop with no height
     ({"image_format": 2}, -1),                                              # unknown pixel type
     ({"image_format": 1, "0.downsample": 2}, -5),                           # float images: full resolution
     ({"image_format": 1, "0.window": 9, "launch": 1}, -5),                  # float images: grid launch
@@ -112,7 +113,7 @@ def test_tsdf_rejects_bad_config():
         for k, v in kw.items():
             setattr(c, k, v)
         return c
-    for kw in ({"voxel_m": 0.0}, {"mu_m": -1.0}, {"w_max": 0.5}, {"max_width": 4},
+    for kw in ({"voxel_m": 0.0}, {"mu_m": -1.0}, {"mu_m": 13.0}, {"w_max": 0.5}, {"max_width": 4},
                {"blocks": (psweep._i32 * 3)(0, 4, 4)}, {"blocks": (psweep._i32 * 3)(1024, 1024, 1024)}):
         with pytest.raises(psweep.PsweepError) as ei:
             psweep.psweep_tsdf_create(cfg(**kw))
@@ -124,6 +125,20 @@ def test_tsdf_rejects_bad_config():
     cam = psweep.psweep_camera(0.9, 100.0, 100.0, 160.0, 128.0, 320, 256)
     pose = psweep.psweep_pose()
     c3 = (psweep._d * 3)(0.0, 0.0, 0.0)
+    pose.R[:] = [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
     assert L.psweep_tsdf_integrate(ts, cam, pose, c3, 1, 0, None) == psweep.ESTATE
     assert L.psweep_tsdf_extract(ts, None, None, None, None) == psweep.ESTATE
+    # arguments are checked before the state: non-finite or non-rotation poses,
+    # and centres whose block coordinates leave the 21-bit key range
+    bad = psweep.psweep_pose()
+    bad.R[:] = [float("nan")] + [0.0] * 8
+    assert L.psweep_tsdf_integrate(ts, cam, bad, c3, 1, 0, None) == psweep.EINVAL
+    bad.R[:] = [2.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
+    assert L.psweep_tsdf_integrate(ts, cam, bad, c3, 1, 0, None) == psweep.EINVAL
+    pose.t[:] = [0.0, float("inf"), 0.0]
+    assert L.psweep_tsdf_integrate(ts, cam, pose, c3, 1, 0, None) == psweep.EINVAL
+    pose.t[:] = [0.0, 0.0, 0.0]
+    far = (psweep._d * 3)(0.0, 0.0, 9.0e5)
+    assert L.psweep_tsdf_integrate(ts, cam, pose, far, 1, 0, None) == psweep.EINVAL
+    assert psweep.psweep_tsdf_last_error(ts)
     psweep.psweep_tsdf_destroy(ts)

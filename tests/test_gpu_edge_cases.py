@@ -2,6 +2,8 @@
 images no larger than the window, textureless images, sources that see
 nothing of the reference view, fewer usable sources than K, and a large
 frame checked on sampled pixels."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -110,3 +112,25 @@ def test_large_frame_sampled():
     s = wta_stats({k: v[pix[:, 1], pix[:, 0]] for k, v in g.items()}, ref, ref["volume"])
     print(s)
     assert_wta_parity(s)
+
+
+def test_non_finite_poses_and_cameras_are_rejected():
+    """set_cameras refuses a NaN rotation, a non-finite translation and a NaN
+    principal point with EINVAL, and leaves the context usable."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1809_06132_amd import psweep as P
+    from paper_1809_06132_amd.sweep import PlaneSweep
+    fr = scenegen.random_small_frame(w=64, h=48, n_src=1, seed=3, f=40.0)
+    st = Settings(levels=[Level(n_fronto=8, near=1.0, far=10.0, window=5)], best_k=1)
+    ps = PlaneSweep(st, 64, 48, 1)
+    good = fr.poses[0]
+    bad_R = dataclasses.replace(good, R=np.where(np.eye(3) > 0, np.nan, 0.0))
+    bad_t = dataclasses.replace(good, t=np.array([np.inf, 0.0, 0.0]))
+    bad_cam = dataclasses.replace(fr.ref_cam, cx=float("nan"))
+    for ref, poses in ((fr.ref_cam, [bad_R]), (fr.ref_cam, [bad_t]), (bad_cam, fr.poses)):
+        with pytest.raises(P.PsweepError) as ei:
+            ps.set_cameras(0, ref, fr.src_cams, poses)
+        assert ei.value.status == -1
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    ps.close()
