@@ -214,13 +214,16 @@ def bench_levels(args):
     if args.workload == "C3":
         wl = scenegen.workload("C3")
         cases = [("C3", wl.frames[0], wl.settings, list(range(3)), st) for st in ("f32", "f16", "bf16")]
+        # both levels in one persistent launch (their tiles balance each other)
+        cases.append(("C3", wl.frames[0], wl.settings, list(range(3)), "f32", "persistent"))
     else:
         wl = scenegen.workload("paper")
         cases = [("paper", wl.frames[0], wl.settings, list(range(4)), "f32"),
                  ("paper", wl.frames[0], wl.settings, [0, 1], "f32")]
-    for name, fr, st, srcs, storage in cases:
+    for name, fr, st, srcs, storage, *launch in cases:
+        launch = launch[0] if launch else "grid"
         W, H = fr.ref_cam.width, fr.ref_cam.height
-        ps = PlaneSweep(st, W, H, len(srcs), storage=storage)
+        ps = PlaneSweep(st, W, H, len(srcs), storage=storage, launch=launch)
         ps.set_cameras(0, fr.ref_cam, [fr.src_cams[i] for i in srcs], [fr.poses[i] for i in srcs])
         d = frame_to_device(fr)
         d["srcs"] = [d["srcs"][i] for i in srcs]
@@ -228,7 +231,8 @@ def bench_levels(args):
         pp = ps.plane_pixels([d])
         med, pct = _time_runs(ps, [d], [out], args.steps, args.warmup)
         ps.close()
-        rows.append({"workload": name, "cameras": len(srcs) + 1, "storage": storage, "ms_per_map": med,
+        rows.append({"workload": name, "cameras": len(srcs) + 1, "storage": storage, "launch": launch,
+                     "ms_per_map": med,
                      "ms_p10_p50_p90": pct, "maps_per_s": 1e3 / med, "plane_pixels_per_map": pp,
                      "gpix_planes_per_s": pp / (med * 1e-3) / 1e9})
     line = {"metric": METRIC, "workload": args.workload, "results": rows}
