@@ -134,7 +134,9 @@ def bench_c5(args):
             w, h = fr.ref_cam.width, fr.ref_cam.height
             ps.set_crop(i, (w - w // 2) // 2, (h - h // 2) // 2, w // 2, h // 2)
 
-    res = {}
+    from paper_1809_06132_amd import autotune
+
+    res, tuned = {}, {}
     # plain: one frame per run, FP32 staging, per-level grid launches
     ps = PlaneSweep(st, W, H, 4, max_frames=1, max_camera_sets=len(frames), storage="f32", launch="grid")
     setup(ps)
@@ -159,6 +161,10 @@ def bench_c5(args):
                         launch=launch)
         setup(ps)
         outs = [ps.alloc_outputs(camera_set=i) for i in range(len(frames))]
+        # tile shape, then plane chunks per level, picked by the autotuner on
+        # this very batch (no cache: tuned afresh every time)
+        choice = autotune.tune(ps, dev, outs, reps=3, cache_path=None)
+        tuned[f"{launch}_{storage}"] = {"tiles": choice["tiles"], "chunks": choice["chunks"]}
         ps.capture_graph(dev, outs)
         for _ in range(args.warmup):
             ps.launch_graph()
@@ -174,6 +180,7 @@ def bench_c5(args):
         line[k] = v
         line[k.replace("_ms", "_gpps")] = pp / (v * 1e-3) / 1e9
     best = min((k for k in res if k.startswith("batched")), key=res.get)
+    line["autotuned"] = tuned
     line["best_batched"] = best
     line["best_batched_vs_plain_f32"] = res["plain_f32_ms"] / res[best]
     print(json.dumps(line), flush=True)
