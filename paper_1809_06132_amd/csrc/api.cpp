@@ -1,7 +1,7 @@
 // Host side of the psweep C ABI (include/psweep.h): argument checks, the
 // workspace layout, FP64 level cameras, the per-run job tables and the launch
 // sequence
-//   table upload -> FP64 plane setup -> level images -> border marks ->
+//   table upload -> FP64 plane setup -> level images and border marks ->
 //   sweep (one grid per level, or one persistent launch) -> level merge.
 #include <hip/hip_runtime.h>
 
@@ -18,7 +18,6 @@ using namespace psw;
 
 extern "C" const void *psw_setup_kernel();
 extern "C" const void *psw_prep_kernel();
-extern "C" const void *psw_border_kernel();
 extern "C" const void *psw_reset_kernel();
 extern "C" const void *psw_merge_kernel();
 extern "C" const void *psw_chunk_merge_kernel();
@@ -665,12 +664,9 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
         PSW_HIP(hipLaunchKernel(psw_setup_kernel(), dim3((maxPS + 255) / 256, nj), dim3(256), a, 0, stream), "setup");
     }
     {
-        void *a[] = {&dp};
+        // level images and the border marks of every job
+        void *a[] = {&dp, &db};
         PSW_HIP(hipLaunchKernel(psw_prep_kernel(), dim3(256, 1 + maxS, nj), dim3(256), a, 0, stream), "prep");
-    }
-    {
-        void *a[] = {&db};
-        PSW_HIP(hipLaunchKernel(psw_border_kernel(), dim3(32, nj), dim3(256), a, 0, stream), "border");
     }
     const int store = cfg.storage, soft = cfg.mode == PSWEEP_MODE_SOFT ? 1 : 0;
     if (timed) {

@@ -48,12 +48,51 @@ __device__ __forceinline__ uint32_t level_pix(const uint8_t *img, int64_t pitch,
     return ((uint32_t)p[0] + p[1] + p[pitch] + p[pitch + 1] + 2u) >> 2;
 }
 
-// blockIdx.z: prep job; blockIdx.y: 0 = reference, 1 + s = source s
-__global__ void prep_kernel(const PrepDev *__restrict__ preps) {
+// invalid marks on the frame of pixels whose window leaves the image
+// (threads t, t + stride, ... of the frame's pixels)
+__device__ void border_marks(const BorderDev &B, int t, int stride) {
+    const int w = B.w, h = B.h, hw = B.hw;
+    const int band = min(hw, h);             // rows at top and at bottom
+    const int top = band * w;
+    const int side_rows = max(h - 2 * band, 0);
+    const int total = 2 * top + side_rows * 2 * min(hw, w);
+    for (int e = t; e < total; e += stride) {
+        int x, y;
+        if (e < 2 * top) {
+            const int r = e / w;
+            x = e % w;
+            y = r < band ? r : h - 2 * band + r;
+        } else {
+            const int q = e - 2 * top, cw = min(hw, w);
+            const int r = q / (2 * cw), c = q % (2 * cw);
+            y = band + r;
+            x = c < cw ? c : w - 2 * cw + c;
+        }
+        if (x < 0 || x >= w || y < 0 || y >= h) continue;
+        const int64_t o = (int64_t)y * B.out_pitch + x;
+        if (B.index) B.index[o] = -1;
+        if (B.delta) B.delta[o] = 0.0f;
+        if (B.cost1) B.cost1[o] = PSW_INF;
+        if (B.cost2) B.cost2[o] = PSW_INF;
+        if (B.depth) B.depth[o] = __builtin_nanf("");
+        if (B.z) B.z[o] = __builtin_nanf("");
+        if (B.level_id) B.level_id[o] = 255;
+        if (B.soft_rho) {
+            const int64_t so = (int64_t)y * B.soft_pitch + x;
+            B.soft_rho[so] = __builtin_nanf("");
+            B.soft_lse[so] = -PSW_INF;
+        }
+    }
+}
+
+// blockIdx.z: job; blockIdx.y: 0 = reference level and the job's border
+// marks, 1 + s = source s
+__global__ void prep_kernel(const PrepDev *__restrict__ preps, const BorderDev *__restrict__ borders) {
     const PrepDev &P = preps[blockIdx.z];
     const int which = blockIdx.y;
     const int ds = P.downsample;
     if (which == 0) {
+        border_marks(borders[blockIdx.z], blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
         if (!P.ref_level) return;
         const int lw = P.ref_w / ds, lh = P.ref_h / ds;
         for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lw * lh; e += gridDim.x * blockDim.x) {
@@ -80,49 +119,36 @@ __global__ void prep_kernel(const PrepDev *__restrict__ preps) {
     }
     const uint8_t *img = static_cast<const uint8_t *>(P.src_full[s]);
     uint32_t *tex = P.tex[s];
+    if (ds == 1 && (lw & 3) == 0 && (pitch & 3) == 0 && ((uintptr_t)img & 3) == 0) {
+        // four texels per thread: two aligned words and one byte per row, one
+        // 16-byte store (rows of the texture start 16-byte aligned: lw % 4 == 0)
+        const int qw = lw >> 2;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < qw * lh; e += gridDim.x * blockDim.x) {
+            const int x = (e % qw) << 2, y = e / qw;
+            const int y1 = min(y + 1, lh - 1);
+            const uint8_t *r0 = img + (int64_t)y * pitch + x, *r1 = img + (int64_t)y1 * pitch + x;
+            const uint32_t a = *reinterpret_cast<const uint32_t *>(r0), b = *reinterpret_cast<const uint32_t *>(r1);
+            // the texel right of the group, clamped at the last column
+            const uint32_t a4 = x + 4 < lw ? r0[4] : (a >> 24), b4 = x + 4 < lw ? r1[4] : (b >> 24);
+            const uint64_t ra = a | ((uint64_t)a4 << 32), rb = b | ((uint64_t)b4 << 32);
+            uint4 q;
+            uint32_t *qs = &q.x;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t p00 = (uint32_t)(ra >> (8 * t)) & 0xffu, p10 = (uint32_t)(ra >> (8 * t + 8)) & 0xffu;
+                const uint32_t p01 = (uint32_t)(rb >> (8 * t)) & 0xffu, p11 = (uint32_t)(rb >> (8 * t + 8)) & 0xffu;
+                qs[t] = p00 | (p10 << 8) | (p01 << 16) | (p11 << 24);
+            }
+            *reinterpret_cast<uint4 *>(tex + (int64_t)y * lw + x) = q;
+        }
+        return;
+    }
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lw * lh; e += gridDim.x * blockDim.x) {
         const int x = e % lw, y = e / lw;
         const int x1 = min(x + 1, lw - 1), y1 = min(y + 1, lh - 1);
         const uint32_t p00 = level_pix(img, pitch, x, y, ds), p10 = level_pix(img, pitch, x1, y, ds);
         const uint32_t p01 = level_pix(img, pitch, x, y1, ds), p11 = level_pix(img, pitch, x1, y1, ds);
         tex[e] = p00 | (p10 << 8) | (p01 << 16) | (p11 << 24);
-    }
-}
-
-// invalid marks on the frame of pixels whose window leaves the image
-__global__ void border_kernel(const BorderDev *__restrict__ bs) {
-    const BorderDev &B = bs[blockIdx.y];
-    const int w = B.w, h = B.h, hw = B.hw;
-    const int band = min(hw, h);             // rows at top and at bottom
-    const int top = band * w;
-    const int side_rows = max(h - 2 * band, 0);
-    const int total = 2 * top + side_rows * 2 * min(hw, w);
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        int x, y;
-        if (e < 2 * top) {
-            const int r = e / w;
-            x = e % w;
-            y = r < band ? r : h - 2 * band + r;
-        } else {
-            const int q = e - 2 * top, cw = min(hw, w);
-            const int r = q / (2 * cw), c = q % (2 * cw);
-            y = band + r;
-            x = c < cw ? c : w - 2 * cw + c;
-        }
-        if (x < 0 || x >= w || y < 0 || y >= h) continue;
-        const int64_t o = (int64_t)y * B.out_pitch + x;
-        if (B.index) B.index[o] = -1;
-        if (B.delta) B.delta[o] = 0.0f;
-        if (B.cost1) B.cost1[o] = PSW_INF;
-        if (B.cost2) B.cost2[o] = PSW_INF;
-        if (B.depth) B.depth[o] = __builtin_nanf("");
-        if (B.z) B.z[o] = __builtin_nanf("");
-        if (B.level_id) B.level_id[o] = 255;
-        if (B.soft_rho) {
-            const int64_t so = (int64_t)y * B.soft_pitch + x;
-            B.soft_rho[so] = __builtin_nanf("");
-            B.soft_lse[so] = -PSW_INF;
-        }
     }
 }
 
@@ -331,7 +357,6 @@ const void *psw_mask_kernel() { return (const void *)&psw::mask_kernel; }
 const void *psw_chunk_merge_kernel() { return (const void *)&psw::chunk_merge_kernel; }
 const void *psw_setup_kernel() { return (const void *)&psw::setup_kernel; }
 const void *psw_prep_kernel() { return (const void *)&psw::prep_kernel; }
-const void *psw_border_kernel() { return (const void *)&psw::border_kernel; }
 const void *psw_reset_kernel() { return (const void *)&psw::reset_counter_kernel; }
 const void *psw_merge_kernel() { return (const void *)&psw::merge_kernel; }
 }
