@@ -729,15 +729,26 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
             if (timed) { PSW_HIP(hipEventRecord(ctx->ev1[0], stream), "event record"); ctx->n_timed = 1; }
         }
     }
-    bool any_chunks = false;
-    for (int j = 0; j < nj; ++j) any_chunks |= (*host_jobs)[j].nch_f + (*host_jobs)[j].nch_g > 1;
-    if (any_chunks) {
+    // the merges run one thread per pixel (their loads depend on each other,
+    // so they need the parallelism), up to 8192 workgroups per job
+    auto blocks_for = [](int64_t px) { return (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (px + 255) / 256)); };
+    int64_t chunk_px = 0;
+    for (int j = 0; j < nj; ++j) {
+        const JobDev &J = (*host_jobs)[j];
+        if (J.nch_f + J.nch_g > 1) chunk_px = std::max<int64_t>(chunk_px, (int64_t)J.w * J.h);
+    }
+    if (chunk_px > 0) {
         void *a[] = {&dj};
-        PSW_HIP(hipLaunchKernel(psw_chunk_merge_kernel(), dim3(512, nj), dim3(256), a, 0, stream), "chunk merge");
+        PSW_HIP(hipLaunchKernel(psw_chunk_merge_kernel(), dim3(blocks_for(chunk_px), nj), dim3(256), a, 0, stream),
+                "chunk merge");
     }
     if (blob.nm > 0) {
+        const MergeDev *hm = reinterpret_cast<const MergeDev *>(blob.bytes.data() + blob.merges);
+        int64_t merge_px = 0;
+        for (int m = 0; m < blob.nm; ++m) merge_px = std::max<int64_t>(merge_px, (int64_t)hm[m].w * hm[m].h);
         void *a[] = {&dm};
-        PSW_HIP(hipLaunchKernel(psw_merge_kernel(), dim3(512, blob.nm), dim3(256), a, 0, stream), "merge");
+        PSW_HIP(hipLaunchKernel(psw_merge_kernel(), dim3(blocks_for(merge_px), blob.nm), dim3(256), a, 0, stream),
+                "merge");
     }
     return PSWEEP_OK;
 }
