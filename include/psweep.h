@@ -250,7 +250,7 @@ psweep_status psweep_mask_boxes(psweep_ctx *ctx, int32_t camera_set, float *dept
 
 /* Plane chunks per tile for one level: each tile's planes are cut into
  * n_chunks contiguous ranges swept by separate workgroups (more parallelism
- * on small images) and combined exactly afterwards; 0 = automatic (about twenty
+ * on small images) and combined exactly afterwards; 0 = automatic (about 28
  * waves per SIMD), 1 = one pass over all planes, at most 8.  Results do not
  * depend on the choice (bitwise, winner-take-all mode). */
 psweep_status psweep_set_chunks(psweep_ctx *ctx, int32_t level, int32_t n_chunks);

@@ -521,13 +521,13 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             J.tiles_x = rc.w > 2 * hw ? (rc.w - 2 * hw + TXO - 1) / TXO : 0;
             J.tiles_y = rc.h > 2 * hw ? (rc.h - 2 * hw + TYO - 1) / TYO : 0;
             J.rows = rows; J.waves = waves;
-            // plane chunks: enough workgroups for about twenty waves per SIMD
+            // plane chunks: enough workgroups for about 28 waves per SIMD
             // over the launch, so that uneven tiles still balance
             {
                 const int ntile = J.tiles_x * J.tiles_y;
                 int nch = ctx->chunks[l];
                 if (nch == 0) {
-                    const long long target = 20LL * ctx->n_cu * 4;
+                    const long long target = 28LL * ctx->n_cu * 4;
                     const long long have = (long long)ntile * waves * (cfg.launch == PSWEEP_LAUNCH_PERSISTENT ? nf : 1);
                     nch = have > 0 ? (int)((target + have - 1) / have) : 1;
                     nch = std::max(1, std::min(nch, kMaxChunks));

@@ -264,7 +264,7 @@ struct Tile {
     using St = Stage<STORE>;
     using ST = typename St::T;
 
-    static constexpr size_t lds_bytes() { return (size_t)S * T * kWave * sizeof(ST); }
+    static constexpr size_t lds_bytes() { return 2 * (size_t)S * T * kWave * sizeof(ST); }
 
     __device__ static void run(const JobDev *__restrict__ Jp, int tile_x, int tile_y, int chunk, char *smem) {
         const JobDev &J = *Jp;
@@ -405,8 +405,9 @@ struct Tile {
 #pragma unroll
             for (int i = 0; i < R; ++i) cprev[i] = PSW_INF;
 
-            for (int kk = 0; kk < np; ++kk) {
-                const int k = k0 + kk;
+            // double-buffered tile: the warp of plane k + 1 goes to the other
+            // buffer while the rows of plane k are read; one barrier per plane
+            auto warp_plane = [&](const int k, ST *buf) {
                 // ---- warp all sources' sample rows of this plane into LDS ----
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -423,7 +424,7 @@ struct Tile {
                     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                         (void *)J.src[s].tex, (short)0, (int)(row_bytes * (uint32_t)J.src[s].h), 0x00020000);
                     const float px = h1x * x, py = h1y * x, pz = h1z * x;
-                    ST *dst = tile + (size_t)s * T * kWave + lane;
+                    ST *dst = buf + (size_t)s * T * kWave + lane;
 #pragma unroll
                     for (int i = 0; i < NWR; ++i) {
                         const int j = wave + NW * i;
@@ -446,14 +447,19 @@ struct Tile {
                         dst[(size_t)j * kWave] = St::put(ok ? b : -0.0f);
                     }
                 }
-                __syncthreads();
-
+            };
+            warp_plane(k0, tile);
+            __syncthreads();
+            for (int kk = 0; kk < np; ++kk) {
+                const int k = k0 + kk;
+                const ST *cur = tile + (size_t)(kk & 1) * S * T * kWave;
+                if (kk + 1 < np) warp_plane(k + 1, tile + (size_t)((kk + 1) & 1) * S * T * kWave);
                 // ---- run down the rows: vertical sums, then window sums ----
                 float vb[S], vbb[S], vab[S];
                 int last_bad[S];
 #pragma unroll
                 for (int s = 0; s < S; ++s) { vb[s] = 0.f; vbb[s] = 0.f; vab[s] = 0.f; last_bad[s] = -1000; }
-                const ST *col = tile + (size_t)(wave * R) * kWave + lane;
+                const ST *col = cur + (size_t)(wave * R) * kWave + lane;
 #pragma unroll
                 for (int m = 0; m < VR; ++m) {
 #pragma unroll
