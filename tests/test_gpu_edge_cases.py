@@ -114,6 +114,27 @@ def test_large_frame_sampled():
     assert_wta_parity(s)
 
 
+def test_maximum_frame_sampled():
+    """The largest frame the library takes, 8192 x 8192 (one source, 48 + 16
+    planes, 7x7), on 400 sampled pixels: every index and offset of the sweep,
+    the plane chunks and their merge at full size."""
+    fr = scenegen._street_frame(8192, 8192, 0.3516 * 8192, 1012, 2012, ss=1)
+    fr = Frame(ref=fr.ref, srcs=fr.srcs[:1], ref_cam=fr.ref_cam, src_cams=fr.src_cams[:1], poses=fr.poses[:1],
+               gt_range=None, gt_z=None)
+    lv = Level(n_fronto=48, near=0.5, far=30.0, n_ground=16, h_lo=-0.5, h_hi=0.5, window=7)
+    st = Settings(levels=[lv], best_k=1)
+    g = _sweep(st, fr)
+    rng = np.random.default_rng(12)
+    pix = np.stack([rng.integers(0, 8192, 400), rng.integers(0, 8192, 400)], 1).astype(np.int32)
+    ref = oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=pix, volume=True)
+    s = wta_stats({k: v[pix[:, 1], pix[:, 0]] for k, v in g.items()}, ref, ref["volume"])
+    print(s)
+    assert_wta_parity(s)
+    # the last row and column of the map are written (border marks included)
+    assert np.all(g["index"][-3:] == -1) and np.all(g["index"][:, -3:] == -1)
+    assert (g["index"] >= 0).mean() > 0.2
+
+
 def test_non_finite_poses_and_cameras_are_rejected():
     """set_cameras refuses a NaN rotation, a non-finite translation and a NaN
     principal point with EINVAL, and leaves the context usable."""
