@@ -114,6 +114,41 @@ def test_large_frame_sampled():
     assert_wta_parity(s)
 
 
+@pytest.mark.parametrize("family,chunks", [("fronto", 1), ("fronto", 4), ("ground", 1), ("ground", 3)])
+def test_exact_ties_pick_the_lowest_plane(family, chunks):
+    """A source at the reference's centre (pure rotation) sees every plane
+    through the same map H = R, so the planes of one family tie exactly: the
+    winner must be the family's first plane on every valid pixel, with
+    cost2 = cost1 and no subpixel step, also when the planes are cut into
+    chunks.  (Across families the costs agree only to rounding: the running
+    window sums of a tile carry the rows above a pixel, and the ground family
+    has none above the horizon.)"""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+    fr = scenegen.random_small_frame(w=120, h=80, n_src=1, seed=3, f=70.0)
+    th = np.radians(2.0)
+    R = np.array([[np.cos(th), 0, np.sin(th)], [0, 1, 0], [-np.sin(th), 0, np.cos(th)]])
+    src = Frame(ref=fr.ref, srcs=[fr.ref], ref_cam=fr.ref_cam, src_cams=[fr.ref_cam], poses=[Pose(R, np.zeros(3))],
+                gt_range=None, gt_z=None)
+    nf, ng = (12, 0) if family == "fronto" else (0, 6)
+    lv = Level(n_fronto=nf, near=1.0, far=20.0, n_ground=ng, h_lo=-0.3, h_hi=0.3, window=5)
+    st = Settings(levels=[lv], best_k=1)
+    ps = PlaneSweep(st, 120, 80, 1)
+    ps.set_cameras(0, src.ref_cam, src.src_cams, src.poses)
+    ps.set_chunks(0, chunks)
+    out = ps.alloc_outputs()
+    ps.run([frame_to_device(src)], [out])
+    torch.cuda.synchronize()
+    g = to_np(out["merged"])
+    ps.close()
+    v = g["index"] >= 0
+    assert v.sum() > (2000 if family == "fronto" else 1000)
+    assert np.all(g["index"][v] == 0)
+    assert np.array_equal(g["cost2"][v], g["cost1"][v])
+    assert np.all(g["delta"][v] == 0.0)
+
+
 def test_maximum_frame_sampled():
     """The largest frame the library takes, 8192 x 8192 (one source, 48 + 16
     planes, 7x7), on 400 sampled pixels: every index and offset of the sweep,
