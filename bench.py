@@ -41,21 +41,36 @@ def algorithmic_ops_per_plane_pixel(n_src: int) -> int:
 # "python bench.py --steps 2 --warmup 1 --no-cpu --copy-calibration", each
 # scaled by what the same counter reads for a 256 MiB device copy (FETCH_SIZE
 # reads half the copied bytes, WRITE_SIZE all of them).  Valid only for the
-# kernel sources they were taken on: a source hash guards them.
+# kernel code they were taken on: a hash of the sources' code (comments and
+# whitespace left out) guards them.
 COUNTED_TRAFFIC = {
-    "sources_sha256": "71167c2305e281af9b0b9a6a5184372170d61bfd5fa76ef2a6e03f3d49848ded",
+    "sources_sha256": "4f5cb7e9c18f1cc28626e79fb90a98ec9e8ec9f82e7eee0a1fff21967b634e2a",
     "fetch_kib": 21093.0, "write_kib": 180160.0, "fetch_scale": 262144.0 / 131090.0, "write_scale": 1.0,
 }
 TRAFFIC_SOURCES = ["paper_1809_06132_amd/csrc/sweep_common.h", "paper_1809_06132_amd/csrc/psweep_internal.h",
                    "paper_1809_06132_amd/csrc/inst_grid.hip", "paper_1809_06132_amd/csrc/api.cpp"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace runs collapsed, so that
+    a comment edit does not count as a kernel change (string literals are
+    kept as they are)."""
+    import re
+    string = r'"(?:\\.|[^"\\])*"'
+    no_comments = re.sub(string + r'|//[^\n]*|/\*.*?\*/',
+                         lambda m: m.group(0) if m.group(0).startswith('"') else " ", text, flags=re.S)
+    parts = re.split("(" + string + ")", no_comments)
+    return "".join(p if i % 2 else re.sub(r"\s+", " ", p) for i, p in enumerate(parts)).strip()
+
+
 def kernel_sources_sha256() -> str:
+    """Hash of the code (not the comments) of the sources the counted traffic
+    depends on."""
     import hashlib
     h = hashlib.sha256()
     for rel in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

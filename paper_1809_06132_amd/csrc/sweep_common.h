@@ -13,7 +13,9 @@
 //     rows; the tile's 64 - (W-1) output columns are the lanes whose whole
 //     window lies inside the 64;
 //   * per plane, the NW waves warp the tile's NW*R + W - 1 sample rows of
-//     every source (rows interleaved across waves) into LDS;
+//     every source (rows interleaved across waves) into LDS; the LDS tile is
+//     double-buffered, so the warp of the next plane overlaps the rows of
+//     this one and one barrier per plane suffices;
 //   * each wave then runs down its R + W - 1 rows with per-lane running
 //     vertical sums of b, b^2 and a*b (one set per source, in registers) and
 //     forms horizontal window sums across lanes with ds_bpermute/DPP shifts;
