@@ -201,9 +201,14 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
  * X_src + v + omega x X_src (d_grad_pose: device doubles [n_src][6] ordered
  * v, omega; overwritten).  Uses the images and soft outputs of the last
  * psweep_run, which must have been a soft run (ESTATE otherwise).  Warps are
- * recomputed, not stored.  Image gradients are accumulated with atomics, so
- * they vary in the last bits from run to run.  Windows 5, 7, 9 and up to three
- * sources (EUNSUPPORTED otherwise). */
+ * recomputed, not stored.  The planes are split into chunks swept by separate
+ * workgroups.  Image gradients are accumulated with atomics, so they vary in
+ * the last bits from run to run.  The pose gradient is summed in a fixed
+ * order, so it does not.  Its per-workgroup partial sums go to the context
+ * workspace (the plane-chunk region of that soft run), so the call must be
+ * ordered after the run and before the next run on the same workspace, like
+ * every call on a context.  Windows 5, 7, 9 and up to three sources
+ * (EUNSUPPORTED otherwise). */
 psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_invdepth,
                                          float *const *d_grad_src, double *d_grad_pose, void *hip_stream);
 

@@ -27,6 +27,7 @@ extern "C" const void *psw_backward_kernel(int win, int n_src, int img, int imag
 extern "C" size_t psw_backward_lds(int win, int n_src);
 extern "C" int psw_backward_tile_rows();
 extern "C" const void *psw_zero_kernel();
+extern "C" const void *psw_pose_reduce_kernel();
 
 namespace {
 
@@ -129,6 +130,7 @@ struct psweep_ctx {
     float *soft_rho = nullptr, *soft_lse = nullptr;
     int64_t soft_pitch = 0;
     size_t soft_job_off = 0;   // device address of the job used by the backward
+    char *soft_part = nullptr;   // that job's plane-chunk region, free once its run is merged
     // graph (captured on a stream of the context's own: the default stream
     // cannot be captured)
     hipGraph_t graph = nullptr;
@@ -801,6 +803,7 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
         ctx->soft_lse = out[0].soft_lse;
         ctx->soft_pitch = out[0].soft_pitch ? out[0].soft_pitch : hj[0].w;
         ctx->soft_job_off = ctx->off_table[0] + blob.jobs;
+        ctx->soft_part = reinterpret_cast<char *>(hj[0].part);
     } else {
         ctx->soft_ready = false;
     }
@@ -898,12 +901,6 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
         void *a[] = {&p, &n};
         PSW_HIP(hipLaunchKernel(zk, dim3(256), dim3(256), a, 0, stream), "zero");
     }
-    {
-        float *p = (float *)d_grad_pose;
-        int64_t n = (int64_t)C.n_src * 12;   // doubles as pairs of floats
-        void *a[] = {&p, &n};
-        PSW_HIP(hipLaunchKernel(zk, dim3(1), dim3(256), a, 0, stream), "zero");
-    }
     const int win = ctx->cfg.level[0].window;
     bool any_image = false;
     for (int s = 0; s < C.n_src; ++s) any_image |= gsrc[s] != nullptr;
@@ -916,13 +913,33 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     const int tyo = psw_backward_tile_rows();
     const int tx = (w - 2 * hw + (kWave - 2 * hw) - 1) / (kWave - 2 * hw);
     const int ty = (h - 2 * hw + tyo - 1) / tyo;
-    if (tx <= 0 || ty <= 0) return PSWEEP_OK;
-    float *g0 = gsrc[0], *g1 = gsrc[1], *g2 = gsrc[2], *g3 = gsrc[3];
-    const float *rho = ctx->soft_rho, *lse = ctx->soft_lse;
-    int64_t sp = ctx->soft_pitch;
-    void *a[] = {(void *)&job, (void *)&d_grad_invdepth, (void *)&rho, (void *)&lse, &sp,
-                 &g0, &g1, &g2, &g3, &d_grad_pose};
-    PSW_HIP(hipLaunchKernel(bk, dim3(tx, ty), dim3(256), a, lds, stream), "backward");
+    const int tiles = tx > 0 && ty > 0 ? tx * ty : 0;
+    // planes in chunks swept by separate workgroups (each plane's share of the
+    // gradient is independent given rho_hat and lse): about 24 waves per
+    // SIMD, at least two planes per chunk
+    const int nf = ctx->cfg.level[0].n_fronto;
+    int nch = tiles ? (int)((24LL * ctx->n_cu * 4 + 4LL * tiles - 1) / (4LL * tiles)) : 1;
+    nch = std::max(1, std::min(std::min(nch, 16), std::max(1, nf / 2)));
+    // the pose gradient: one partial row of 6 S doubles per workgroup, in the
+    // plane-chunk region of the soft run (merged by then), summed in order
+    double *gpart = reinterpret_cast<double *>(ctx->soft_part);
+    const int n_rows = tiles * nch, n_pose = 6 * C.n_src;
+    const size_t part_bytes = align_up((size_t)ctx->ref_w[0] * ctx->ref_h[0] * 4 * kPartWords * kMaxChunks);
+    if ((size_t)n_rows * n_pose * sizeof(double) > part_bytes)
+        return fail(ctx, PSWEEP_EUNSUPPORTED, "backward partial sums exceed the workspace region");
+    if (tiles) {
+        float *g0 = gsrc[0], *g1 = gsrc[1], *g2 = gsrc[2], *g3 = gsrc[3];
+        const float *rho = ctx->soft_rho, *lse = ctx->soft_lse;
+        int64_t sp = ctx->soft_pitch;
+        void *a[] = {(void *)&job, (void *)&d_grad_invdepth, (void *)&rho, (void *)&lse, &sp,
+                     &g0, &g1, &g2, &g3, &gpart};
+        PSW_HIP(hipLaunchKernel(bk, dim3(tx, ty, nch), dim3(256), a, lds, stream), "backward");
+    }
+    {
+        int nr = n_rows, np = n_pose;
+        void *a[] = {&gpart, &nr, &np, &d_grad_pose};
+        PSW_HIP(hipLaunchKernel(psw_pose_reduce_kernel(), dim3(n_pose), dim3(256), a, 0, stream), "pose reduce");
+    }
     return PSWEEP_OK;
 }
 

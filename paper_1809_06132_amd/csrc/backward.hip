@@ -68,7 +68,7 @@ struct Backward {
 
     __device__ static void run(const JobDev *__restrict__ Jp, const float *__restrict__ gin,
                                const float *__restrict__ rho_hat, const float *__restrict__ lse, int64_t spitch,
-                               float *const gsrc[4], double *__restrict__ gpose, char *smem) {
+                               float *const gsrc[4], double *__restrict__ gpart, char *smem) {
         const JobDev &J = *Jp;
         float *tile = reinterpret_cast<float *>(smem);
         float *chan = tile + (size_t)S * T * kWave;   // [s][c][output row][lane]
@@ -153,7 +153,12 @@ struct Backward {
             for (int a = 0; a < 6; ++a) acc[s][a] = 0.0;
         const int K = J.best_k;
 
-        for (int k = 0; k < J.n_fronto; ++k) {
+        // this workgroup's planes: chunk blockIdx.z of gridDim.z even ranges
+        // (each plane's contribution is independent given rho_hat and lse)
+        const int nchunk = (int)gridDim.z, chunk = (int)blockIdx.z;
+        const int k_lo = (int)((int64_t)chunk * J.n_fronto / nchunk);
+        const int k_hi = (int)((int64_t)(chunk + 1) * J.n_fronto / nchunk);
+        for (int k = k_lo; k < k_hi; ++k) {
             const float theta = cptr(J.theta)[k];
             // ---- forward recompute: warped rows of every source into LDS ----
 #pragma unroll
@@ -396,7 +401,10 @@ struct Backward {
             }
             __syncthreads();
         }
-        // ---- pose gradient: wave reduction, one FP64 atomic per wave ----
+        // ---- pose gradient: wave reduction, then the workgroup's partial sum
+        // (one row of gpart per workgroup; a second kernel adds the rows in a
+        // fixed order).  The LDS tile is free: the plane loop ended on a barrier.
+        double *red = reinterpret_cast<double *>(smem);   // [wave][6 S]
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -404,8 +412,16 @@ struct Backward {
                 double v = acc[s][a];
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-                if (lane == 0 && v != 0.0) unsafeAtomicAdd(gpose + s * 6 + a, v);   // device memory: hardware FP64 add
+                if (lane == 0) red[wave * 6 * S + s * 6 + a] = v;
             }
+        __syncthreads();
+        if (wave == 0 && lane < 6 * S) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += red[w * 6 * S + lane];
+            const int64_t wg = (int64_t)blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+            gpart[wg * 6 * S + lane] = t;
+        }
     }
 };
 
@@ -413,16 +429,35 @@ template <int WIN, int S, int IMG, bool GI>
 __global__ __launch_bounds__(256) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
                                                         const float *__restrict__ rho, const float *__restrict__ lse,
                                                         int64_t spitch, float *g0, float *g1, float *g2, float *g3,
-                                                        double *gpose) {
+                                                        double *gpart) {
     extern __shared__ char smem[];
     float *gs[4] = {g0, g1, g2, g3};
-    Backward<WIN, S, IMG, GI>::run(job, gin, rho, lse, spitch, gs, gpose, smem);
+    Backward<WIN, S, IMG, GI>::run(job, gin, rho, lse, spitch, gs, gpart, smem);
+}
+
+// Sum of the workgroups' pose partial rows: workgroup c adds column c, each
+// of its 256 threads a strided share of the rows, then a fixed tree (the
+// same order every time).
+__global__ __launch_bounds__(256) void pose_reduce_kernel(const double *__restrict__ gpart, int n_rows, int n,
+                                                          double *__restrict__ gpose) {
+    __shared__ double part[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    double acc = 0.0;
+    for (int r = t; r < n_rows; r += 256) acc += gpart[(int64_t)r * n + c];
+    part[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0) gpose[c] = part[0];
 }
 
 }  // namespace psw
 
 extern "C" {
 const void *psw_zero_kernel() { return (const void *)&psw::zero_kernel; }
+const void *psw_pose_reduce_kernel() { return (const void *)&psw::pose_reduce_kernel; }
 
 const void *psw_backward_kernel(int win, int n_src, int img, int image_grads) {
 #define PSW_B(W, I, G)                                                                   \
