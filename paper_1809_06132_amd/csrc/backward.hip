@@ -16,9 +16,11 @@
 // Each sample's gradient then goes through the bilinear interpolant to the
 // four source texels (atomics) and through the projection to the pose.
 //
-// Tile layout: 4 waves, lane = sample column, 4 output rows per wave (the
-// four channels of every output pixel then fit in 32 KB of LDS for two
-// sources, so several workgroups share a CU).  Every wave owns a contiguous
+// Tile layout: 4 waves, lane = sample column, 4 output rows per wave.  Per
+// output pixel the channels G/D, G Z/s_bb and G Z bbar/s_bb of every source
+// and the reference mean abar (shared by the sources; sum(G abar/D) is formed
+// from G/D and abar while summing) take 28 KB of LDS for two sources, so four
+// workgroups share a CU.  Every wave owns a contiguous
 // block of the tile's sample rows: it warps them into LDS, and after the
 // channels are written it walks down the block keeping running sums of the
 // channels over the output rows whose window holds the current sample row
@@ -61,10 +63,10 @@ struct Backward {
     static constexpr int T = TYO + 2 * HW;
     static constexpr int RS = (T + NW - 1) / NW;   // contiguous sample rows per wave
     static constexpr int VR = R + 2 * HW;
-    static constexpr int NCH = 4;
+    static constexpr int NCH = 3;   // channels per source; plus one plane of abar
 
     static constexpr size_t lds_tile() { return (size_t)S * T * kWave * 4; }
-    static constexpr size_t lds_bytes() { return lds_tile() + (size_t)NCH * S * TYO * kWave * 4; }
+    static constexpr size_t lds_bytes() { return lds_tile() + (size_t)(NCH * S + 1) * TYO * kWave * 4; }
 
     __device__ static void run(const JobDev *__restrict__ Jp, const float *__restrict__ gin,
                                const float *__restrict__ rho_hat, const float *__restrict__ lse, int64_t spitch,
@@ -72,6 +74,7 @@ struct Backward {
         const JobDev &J = *Jp;
         float *tile = reinterpret_cast<float *>(smem);
         float *chan = tile + (size_t)S * T * kWave;   // [s][c][output row][lane]
+        float *abar = chan + (size_t)NCH * S * TYO * kWave;   // [output row][lane]
         const int lane = threadIdx.x & (kWave - 1);
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
         const int W = J.w, H = J.h;
@@ -146,6 +149,9 @@ struct Backward {
                 }
             }
         }
+        // the reference means of this wave's output rows, for every plane
+#pragma unroll
+        for (int i = 0; i < R; ++i) abar[(size_t)(wave * R + i) * kWave + lane] = mean_a[i];
         double acc[S][6];
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -258,9 +264,8 @@ struct Backward {
                             // unusable windows hold NaN/inf statistics: select, never multiply by 0
                             float *ch = chan + (((size_t)s * NCH) * TYO + wave * R + i) * kWave + lane;
                             ch[0] = chosen ? G * invD : 0.0f;
-                            ch[(size_t)TYO * kWave] = chosen ? G * mean_a[i] * invD : 0.0f;
-                            ch[(size_t)2 * TYO * kWave] = chosen ? G * zs[s] * varb_inv : 0.0f;
-                            ch[(size_t)3 * TYO * kWave] = chosen ? G * zs[s] * bbar * varb_inv : 0.0f;
+                            ch[(size_t)TYO * kWave] = chosen ? G * zs[s] * varb_inv : 0.0f;
+                            ch[(size_t)2 * TYO * kWave] = chosen ? G * zs[s] * bbar * varb_inv : 0.0f;
                         }
                     }
                 }
@@ -286,11 +291,13 @@ struct Backward {
                 // running sums of the channels over the output rows whose
                 // window holds sample row j: rows [j - 2 HW, j] within the tile
                 const float *chs = chan + ((size_t)s * NCH) * TYO * kWave + lane;
+                const float *abs_ = abar + lane;
                 float rA = 0.f, rB = 0.f, rC = 0.f, rE = 0.f;
                 for (int r = j0 - 1 - 2 * HW < 0 ? 0 : j0 - 1 - 2 * HW; r <= j0 - 1 && r < TYO; ++r) {
                     const float *ch = chs + (size_t)r * kWave;
-                    rA += ch[0]; rB += ch[(size_t)TYO * kWave];
-                    rC += ch[(size_t)2 * TYO * kWave]; rE += ch[(size_t)3 * TYO * kWave];
+                    const float a = ch[0];
+                    rA += a; rB = fmaf(a, abs_[(size_t)r * kWave], rB);
+                    rC += ch[(size_t)TYO * kWave]; rE += ch[(size_t)2 * TYO * kWave];
                 }
                 // pose terms of this plane in FP32 (at most RS per lane), then FP64
                 float ps[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -304,13 +311,16 @@ struct Backward {
                     if (j >= T) break;
                     if (j < TYO) {
                         const float *ch = chs + (size_t)j * kWave;
-                        rA += ch[0]; rB += ch[(size_t)TYO * kWave];
-                        rC += ch[(size_t)2 * TYO * kWave]; rE += ch[(size_t)3 * TYO * kWave];
+                        const float a = ch[0];
+                        rA += a; rB = fmaf(a, abs_[(size_t)j * kWave], rB);
+                        rC += ch[(size_t)TYO * kWave]; rE += ch[(size_t)2 * TYO * kWave];
                     }
                     if (j - 2 * HW - 1 >= 0) {
-                        const float *ch = chs + (size_t)(j - 2 * HW - 1) * kWave;
-                        rA -= ch[0]; rB -= ch[(size_t)TYO * kWave];
-                        rC -= ch[(size_t)2 * TYO * kWave]; rE -= ch[(size_t)3 * TYO * kWave];
+                        const int jo = j - 2 * HW - 1;
+                        const float *ch = chs + (size_t)jo * kWave;
+                        const float a = ch[0];
+                        rA -= a; rB = fmaf(-a, abs_[(size_t)jo * kWave], rB);
+                        rC -= ch[(size_t)TYO * kWave]; rE -= ch[(size_t)2 * TYO * kWave];
                     }
                     const float sA = wsum<WIN>(rA, sh), sB = wsum<WIN>(rB, sh);
                     const float sC = wsum<WIN>(rC, sh), sE = wsum<WIN>(rE, sh);
