@@ -152,11 +152,13 @@ struct Backward {
         // the reference means of this wave's output rows, for every plane
 #pragma unroll
         for (int i = 0; i < R; ++i) abar[(size_t)(wave * R + i) * kWave + lane] = mean_a[i];
-        double acc[S][6];
+        // pose terms: FP32 per lane over this chunk's planes, FP64 from the
+        // wave reduction on
+        float acc[S][6];
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int a = 0; a < 6; ++a) acc[s][a] = 0.0;
+            for (int a = 0; a < 6; ++a) acc[s][a] = 0.0f;
         const int K = J.best_k;
 
         // this workgroup's planes: chunk blockIdx.z of gridDim.z even ranges
@@ -405,9 +407,9 @@ struct Backward {
                     if (ca1 >= 0) gadd(grs, ca1, cv1);
                 }
 #pragma unroll
-                for (int a = 0; a < 3; ++a) acc[s][a] += (double)(ps[a] * theta);
+                for (int a = 0; a < 3; ++a) acc[s][a] = fmaf(ps[a], theta, acc[s][a]);
 #pragma unroll
-                for (int a = 3; a < 6; ++a) acc[s][a] += (double)ps[a];
+                for (int a = 3; a < 6; ++a) acc[s][a] += ps[a];
             }
             __syncthreads();
         }
@@ -419,7 +421,7 @@ struct Backward {
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int a = 0; a < 6; ++a) {
-                double v = acc[s][a];
+                double v = (double)acc[s][a];
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
                 if (lane == 0) red[wave * 6 * S + s * 6 + a] = v;
