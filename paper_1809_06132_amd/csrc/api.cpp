@@ -157,8 +157,9 @@ psweep_status hip_fail(psweep_ctx *c, hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
     } while (0)
 
-// bytes of one quad-packed source texel: 4 x u8, or 4 x float
-size_t texel_bytes(const psweep_config &c) { return c.image_format == PSWEEP_IMAGE_F32 ? 16 : 4; }
+// bytes of one source texel: 4 x FP16 bilinear coefficients (u8 images), or
+// the 2x2 cell as 4 x float
+size_t texel_bytes(const psweep_config &c) { return c.image_format == PSWEEP_IMAGE_F32 ? 16 : 8; }
 
 bool single_full(const psweep_config &c) {
     return c.n_levels == 1 && c.level[0].downsample == 1 && c.level[0].crop_w == 0;

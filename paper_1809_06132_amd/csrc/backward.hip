@@ -194,9 +194,8 @@ struct Backward {
                     const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= sd.wm1) & (v >= 0.0f) & (v <= sd.hm1);
                     const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                     const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
-                    const auto q = Texel<IMG>::load(rs, off);
-                    const float top = fmaf(al, q.p10 - q.p00, q.p00), bot = fmaf(al, q.p11 - q.p01, q.p01);
-                    tile[((size_t)s * T + j) * kWave + lane] = ok ? fmaf(be, bot - top, top - 128.0f) : -0.0f;
+                    const float b = Texel<IMG>::sample(rs, off, al, be);
+                    tile[((size_t)s * T + j) * kWave + lane] = ok ? b : -0.0f;
                 }
             }
             __syncthreads();
@@ -347,16 +346,15 @@ struct Backward {
                         const int i1 = i0 + 1 < sd.w ? i0 + 1 : sd.w - 1;
                         const int v1 = v0 + 1 < sd.h ? v0 + 1 : sd.h - 1;
                         const float al = u - (float)i0, be = v - (float)v0;
-                        const auto q = Texel<IMG>::load(rs, __umul24((uint32_t)v0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes);
-                        const float p00 = q.p00, p10 = q.p10, p01 = q.p01, p11 = q.p11;
+                        float dbu, dbv;
+                        Texel<IMG>::slope(rs, __umul24((uint32_t)v0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes, al, be,
+                                          &dbu, &dbv);
                         a00 = (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i0 * 4u);
                         a10 = (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i1 * 4u);
                         a01 = (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i0 * 4u);
                         a11 = (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i1 * 4u);
                         c00 = gb * (1.0f - al) * (1.0f - be); c10 = gb * al * (1.0f - be);
                         c01 = gb * (1.0f - al) * be; c11 = gb * al * be;
-                        const float dbu = fmaf(be, p11 - p01, (1.0f - be) * (p10 - p00));
-                        const float dbv = fmaf(al, p11 - p10, (1.0f - al) * (p01 - p00));
                         // (X, Y, Z) = H (x, y, tau) is the source point P divided by
                         // sigma = 1 / (theta tau) (fronto planes).  With
                         // xu = X / den, yv = Y / den, Au = dbu fx / den,

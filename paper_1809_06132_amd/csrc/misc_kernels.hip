@@ -40,12 +40,25 @@ __global__ void setup_kernel(const SetupDev *__restrict__ jobs) {
 }
 
 // ---------------------------------------------------------------------------
-// level images: 2x2 box-downsampled reference, 2x2-quad packed source texels
+// level images: 2x2 box-downsampled reference, source textures of bilinear
+// cell coefficients
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t level_pix(const uint8_t *img, int64_t pitch, int x, int y, int ds) {
     if (ds == 1) return img[(int64_t)y * pitch + x];
     const uint8_t *p = img + (int64_t)(2 * y) * pitch + 2 * x;
     return ((uint32_t)p[0] + p[1] + p[pitch] + p[pitch + 1] + 2u) >> 2;
+}
+
+// bilinear coefficients of a 2x2 cell as the sweep reads them: FP16 c0 =
+// p00 - 128, c1 = p10 - p00, c2 = p01 - p00, c3 = p11 - p10 - p01 + p00
+// (integers of magnitude <= 510, exact in FP16), packed (c0 | c1 << 16,
+// c2 | c3 << 16)
+__device__ __forceinline__ uint32_t half_bits(int c) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)c);
+}
+__device__ __forceinline__ uint2 coef_texel(uint32_t p00, uint32_t p10, uint32_t p01, uint32_t p11) {
+    const int a = (int)p00, b = (int)p10, c = (int)p01, d = (int)p11;
+    return make_uint2(half_bits(a - 128) | (half_bits(b - a) << 16), half_bits(c - a) | (half_bits(d - b - c + a) << 16));
 }
 
 // invalid marks on the frame of pixels whose window leaves the image
@@ -118,10 +131,10 @@ __global__ void prep_kernel(const PrepDev *__restrict__ preps, const BorderDev *
         return;
     }
     const uint8_t *img = static_cast<const uint8_t *>(P.src_full[s]);
-    uint32_t *tex = P.tex[s];
+    uint2 *tex = reinterpret_cast<uint2 *>(P.tex[s]);
     if (ds == 1 && (lw & 3) == 0 && (pitch & 3) == 0 && ((uintptr_t)img & 3) == 0) {
-        // four texels per thread: two aligned words and one byte per row, one
-        // 16-byte store (rows of the texture start 16-byte aligned: lw % 4 == 0)
+        // four texels per thread: two aligned words and one byte per row, two
+        // 16-byte stores (rows of the texture start 32-byte aligned: lw % 4 == 0)
         const int qw = lw >> 2;
         for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < qw * lh; e += gridDim.x * blockDim.x) {
             const int x = (e % qw) << 2, y = e / qw;
@@ -131,15 +144,16 @@ __global__ void prep_kernel(const PrepDev *__restrict__ preps, const BorderDev *
             // the texel right of the group, clamped at the last column
             const uint32_t a4 = x + 4 < lw ? r0[4] : (a >> 24), b4 = x + 4 < lw ? r1[4] : (b >> 24);
             const uint64_t ra = a | ((uint64_t)a4 << 32), rb = b | ((uint64_t)b4 << 32);
-            uint4 q;
-            uint32_t *qs = &q.x;
+            uint2 q[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const uint32_t p00 = (uint32_t)(ra >> (8 * t)) & 0xffu, p10 = (uint32_t)(ra >> (8 * t + 8)) & 0xffu;
                 const uint32_t p01 = (uint32_t)(rb >> (8 * t)) & 0xffu, p11 = (uint32_t)(rb >> (8 * t + 8)) & 0xffu;
-                qs[t] = p00 | (p10 << 8) | (p01 << 16) | (p11 << 24);
+                q[t] = coef_texel(p00, p10, p01, p11);
             }
-            *reinterpret_cast<uint4 *>(tex + (int64_t)y * lw + x) = q;
+            uint4 *dst = reinterpret_cast<uint4 *>(tex + (int64_t)y * lw + x);
+            dst[0] = make_uint4(q[0].x, q[0].y, q[1].x, q[1].y);
+            dst[1] = make_uint4(q[2].x, q[2].y, q[3].x, q[3].y);
         }
         return;
     }
@@ -148,7 +162,7 @@ __global__ void prep_kernel(const PrepDev *__restrict__ preps, const BorderDev *
         const int x1 = min(x + 1, lw - 1), y1 = min(y + 1, lh - 1);
         const uint32_t p00 = level_pix(img, pitch, x, y, ds), p10 = level_pix(img, pitch, x1, y, ds);
         const uint32_t p01 = level_pix(img, pitch, x, y1, ds), p11 = level_pix(img, pitch, x1, y1, ds);
-        tex[e] = p00 | (p10 << 8) | (p01 << 16) | (p11 << 24);
+        tex[e] = coef_texel(p00, p10, p01, p11);
     }
 }
 

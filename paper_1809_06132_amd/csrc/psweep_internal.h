@@ -13,7 +13,7 @@ constexpr int kWave = 64;
 
 // One source camera of one level, as the sweep kernel reads it.
 struct SrcDev {
-    const uint32_t *tex;   // 2x2-quad packed texels (u8 x 4 or float x 4), row pitch = w texels
+    const uint32_t *tex;   // texels (4 x FP16 cell coefficients or 4 x float), row pitch = w texels
     int32_t w, h;
     float fx, fy, cx, cy, xi;
     float wm1, hm1;        // w - 1, h - 1 (inclusive sample bounds)
@@ -86,7 +86,7 @@ struct SetupDev {
 };
 
 // Level-image preparation for one (frame, level): downsampled reference (if
-// any) and the quad-packed source textures.
+// any) and the source textures.
 struct PrepDev {
     const uint8_t *ref_full;
     int64_t ref_pitch;
@@ -96,7 +96,7 @@ struct PrepDev {
     const void *src_full[kMaxSrc]; // uint8_t or float images (img)
     int64_t src_pitch[kMaxSrc];    // elements
     int32_t src_w[kMaxSrc], src_h[kMaxSrc];   // full-resolution sizes
-    uint32_t *tex[kMaxSrc];        // level-size quad textures: one u32 (4 x u8) or 4 floats per texel
+    uint32_t *tex[kMaxSrc];        // level-size textures: 4 x FP16 cell coefficients or 4 floats per texel
     int32_t img, pad;
 };
 

@@ -135,18 +135,31 @@ __device__ __forceinline__ double wsum_d(double v, const Shifts &sh) {
     return window_sum<WIN>(v, sh, shr1_d, lane_from_d);
 }
 
-// One bilinear sample of a quad-packed source texture at texel (iu, iv) with
-// weights (al, be), centred (minus 128).  IMG 0: a u32 holds the 2x2 grey
-// levels; IMG 1: four floats.  Reads outside the buffer return 0.
+// Bilinear sampling of a source texture at texel (iu, iv) with weights
+// (al, be), value centred (minus 128), and its slopes along u and v.
+// IMG 0: a texel holds the bilinear coefficients of its 2x2 cell as four
+// FP16 integers, c0 = p00 - 128, c1 = p10 - p00, c2 = p01 - p00,
+// c3 = p11 - p10 - p01 + p00 (exact: |c| <= 510), so that
+// b = c0 + al c1 + be (c2 + al c3), three mixed-precision FMAs with FP32
+// rounding; IMG 1: four floats p00, p10, p01, p11.  Reads outside the buffer
+// return 0.
+struct Half2 { _Float16 lo, hi; };
+__device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(Half2, w).lo; }
+__device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(Half2, w).hi; }
 template <int IMG>
 struct Texel;
 template <>
 struct Texel<0> {
-    static constexpr uint32_t bytes = 4;
-    struct Quad { float p00, p10, p01, p11; };
-    __device__ static Quad load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-        const uint32_t q = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
-        return {(float)(q & 0xffu), (float)((q >> 8) & 0xffu), (float)((q >> 16) & 0xffu), (float)(q >> 24)};
+    static constexpr uint32_t bytes = 8;
+    __device__ static float sample(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+        const float t = fmaf(al, half_hi(q[1]), half_lo(q[1]));
+        return fmaf(al, half_hi(q[0]), fmaf(be, t, half_lo(q[0])));
+    }
+    __device__ static void slope(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be, float *du, float *dv) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+        *du = fmaf(be, half_hi(q[1]), half_hi(q[0]));
+        *dv = fmaf(al, half_hi(q[1]), half_lo(q[1]));
     }
     __device__ static float ref(const uint8_t *p, int64_t i) { return (float)gptr(p)[i]; }
 };
@@ -157,6 +170,17 @@ struct Texel<1> {
     __device__ static Quad load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
         return {__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3])};
+    }
+    __device__ static float sample(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be) {
+        const Quad q = load(rs, off);
+        const float top = fmaf(al, q.p10 - q.p00, q.p00);
+        const float bot = fmaf(al, q.p11 - q.p01, q.p01);
+        return fmaf(be, bot - top, top - 128.0f);
+    }
+    __device__ static void slope(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be, float *du, float *dv) {
+        const Quad q = load(rs, off);
+        *du = fmaf(be, q.p11 - q.p01, (1.0f - be) * (q.p10 - q.p00));
+        *dv = fmaf(al, q.p11 - q.p10, (1.0f - al) * (q.p01 - q.p00));
     }
     __device__ static float ref(const uint8_t *p, int64_t i) {
         return gptr(reinterpret_cast<const float *>(p))[i];
@@ -273,6 +297,7 @@ struct Tile {
         ST *tile = reinterpret_cast<ST *>(smem);
         const int lane = threadIdx.x & (kWave - 1);
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        __builtin_assume(wave >= 0 && wave < NW);   // lets the warp rows' loads issue as one batch
         const int W = J.w, H = J.h;
         const int sc = tile_x * TXO + lane;            // sample column of this lane
         const int sr0 = tile_y * TYO;                  // first sample row of the tile
@@ -442,10 +467,7 @@ struct Tile {
                         const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= wm1) & (v >= 0.0f) & (v <= hm1);
                         const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                         const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
-                        const auto q = Texel<IMG>::load(rs, off);
-                        const float top = fmaf(al, q.p10 - q.p00, q.p00);
-                        const float bot = fmaf(al, q.p11 - q.p01, q.p01);
-                        const float b = fmaf(be, bot - top, top - 128.0f);
+                        const float b = Texel<IMG>::sample(rs, off, al, be);
                         dst[(size_t)j * kWave] = St::put(ok ? b : -0.0f);
                     }
                 }
@@ -493,8 +515,9 @@ struct Tile {
                             const float hb = wsum<WIN>(vb[s], sh);
                             const float hbb = wsum<WIN>(vbb[s], sh);
                             const float hab = wsum<WIN>(vab[s], sh);
+                            // scalar work only, no branch: an empty ballot dilates to 0
                             const uint64_t bm = __builtin_amdgcn_ballot_w64(last_bad[s] > m - WIN);
-                            const bool bad = bm != 0 && __builtin_amdgcn_inverse_ballot_w64(dilate<WIN>(bm));
+                            const bool bad = __builtin_amdgcn_inverse_ballot_w64(dilate<WIN>(bm));
                             const float cov = fmaf(-mean_a[i], hb, hab);
                             const float varb = fmaf(-hb * invN, hb, hbb);
                             float zn = cov * isd_a[i] * __builtin_amdgcn_rsqf(varb);
@@ -510,7 +533,7 @@ struct Tile {
                             const bool nb = C < c1[i];
                             const bool fill = (kb[i] == k - 1) && (kk > 0);
                             cp[i] = nb ? PSW_INF : (fill ? C : cp[i]);
-                            c2[i] = nb ? c1[i] : fminf(c2[i], C);
+                            c2[i] = nb ? c1[i] : (C < c2[i] ? C : c2[i]);   // C is never NaN
                             cm[i] = nb ? cprev[i] : cm[i];
                             kb[i] = nb ? k : kb[i];
                             c1[i] = nb ? C : c1[i];

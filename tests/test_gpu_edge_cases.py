@@ -151,23 +151,30 @@ def test_exact_ties_pick_the_lowest_plane(family, chunks):
 
 def test_maximum_frame_sampled():
     """The largest frame the library takes, 8192 x 8192 (one source, 48 + 16
-    planes, 7x7), on 400 sampled pixels: every index and offset of the sweep,
-    the plane chunks and their merge at full size."""
+    planes, 7x7), on 40,000 sampled pixels (about 3,400 oracle-valid): every
+    index and offset of the sweep, the plane chunks and their merge at full
+    size.  The variance floor is 9 grey levels squared per sample (window
+    deviation at least 3 levels).  At this size FP32 source coordinates near
+    8,000 px resolve about 1e-3 px, and the scene's texture is smooth at this
+    scale: with the default floor of 1, windows of 1 to 1.5 levels of
+    deviation pass, where ZNCC turns a 1e-3-level interpolation difference
+    into a cost difference of about 1e-3, and the FP32 maps then leave the
+    oracle's bar on a few pixels in a thousand."""
     fr = scenegen._street_frame(8192, 8192, 0.3516 * 8192, 1012, 2012, ss=1)
     fr = Frame(ref=fr.ref, srcs=fr.srcs[:1], ref_cam=fr.ref_cam, src_cams=fr.src_cams[:1], poses=fr.poses[:1],
                gt_range=None, gt_z=None)
     lv = Level(n_fronto=48, near=0.5, far=30.0, n_ground=16, h_lo=-0.5, h_hi=0.5, window=7)
-    st = Settings(levels=[lv], best_k=1)
+    st = Settings(levels=[lv], best_k=1, var_floor=9.0)
     g = _sweep(st, fr)
     rng = np.random.default_rng(12)
-    pix = np.stack([rng.integers(0, 8192, 400), rng.integers(0, 8192, 400)], 1).astype(np.int32)
+    pix = np.stack([rng.integers(0, 8192, 40000), rng.integers(0, 8192, 40000)], 1).astype(np.int32)
     ref = oracle.sweep_level(lv, st, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, pixels=pix, volume=True)
     s = wta_stats({k: v[pix[:, 1], pix[:, 0]] for k, v in g.items()}, ref, ref["volume"])
     print(s)
     assert_wta_parity(s)
     # the last row and column of the map are written (border marks included)
     assert np.all(g["index"][-3:] == -1) and np.all(g["index"][:, -3:] == -1)
-    assert (g["index"] >= 0).mean() > 0.2
+    assert (g["index"] >= 0).mean() > 0.05   # about 8.5 % of the frame clears the floor
 
 
 def test_non_finite_poses_and_cameras_are_rejected():
