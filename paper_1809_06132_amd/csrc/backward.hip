@@ -191,7 +191,9 @@ struct Backward {
                     const float inv = __builtin_amdgcn_rcpf(den);
                     const float u = fmaf(X * inv, sd.fx, sd.cx);
                     const float v = fmaf(Y * inv, sd.fy, sd.cy);
-                    const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= sd.wm1) & (v >= 0.0f) & (v <= sd.hm1);
+                    // the sweep's validity test (bit patterns: 0 <= u <= wm1)
+                    const bool ok = (den > 0.0f) & (__float_as_uint(u) <= __float_as_uint(sd.wm1)) &
+                                    (__float_as_uint(v) <= __float_as_uint(sd.hm1));
                     const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                     const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
                     const float b = Texel<IMG>::sample(rs, off, al, be);

@@ -464,7 +464,11 @@ struct Tile {
                         const float inv = __builtin_amdgcn_rcpf(den);
                         const float u = fmaf(X * inv, sfx, scx);
                         const float v = fmaf(Y * inv, sfy, scy);
-                        const bool ok = (den > 0.0f) & (u >= 0.0f) & (u <= wm1) & (v >= 0.0f) & (v <= hm1);
+                        // 0 <= u <= wm1 as one unsigned compare of the bit patterns
+                        // (non-negative floats order like their bits; negative
+                        // values and NaN compare above wm1; u is never -0 here)
+                        const bool ok = (den > 0.0f) & (__float_as_uint(u) <= __float_as_uint(wm1)) &
+                                        (__float_as_uint(v) <= __float_as_uint(hm1));
                         const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                         const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
                         const float b = Texel<IMG>::sample(rs, off, al, be);
@@ -530,13 +534,15 @@ struct Tile {
                         C = ((ref_ok >> i) & 1u) ? C : PSW_INF;
                         if (kk == 0) cfirst[i] = C;
                         if (!SOFT) {
+                            // branch-free: with c1 <= c2 (no NaN reaches here) the new
+                            // second best is med3(c1, c2, C) and the new best min(c1, C)
                             const bool nb = C < c1[i];
                             const bool fill = (kb[i] == k - 1) && (kk > 0);
                             cp[i] = nb ? PSW_INF : (fill ? C : cp[i]);
-                            c2[i] = nb ? c1[i] : (C < c2[i] ? C : c2[i]);   // C is never NaN
+                            c2[i] = __builtin_amdgcn_fmed3f(c1[i], c2[i], C);
                             cm[i] = nb ? cprev[i] : cm[i];
                             kb[i] = nb ? k : kb[i];
-                            c1[i] = nb ? C : c1[i];
+                            c1[i] = __builtin_amdgcn_fmed3f(c1[i], C, -PSW_INF);
                             cprev[i] = C;
                         } else if (C < PSW_INF) {
                             const float l = -C * invT;
