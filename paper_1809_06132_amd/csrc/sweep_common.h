@@ -227,11 +227,14 @@ __device__ __forceinline__ float aggregate(const float c[4], int K) {
         m0 = fminf(a0, a2); m3 = fmaxf(a1, a3);
         m1 = fminf(t0, t1); m2 = fmaxf(t0, t1);
     }
-    float acc = m0, cnt = 1.0f;
-    if (K >= 2) { const bool f = m1 < PSW_INF; acc += f ? m1 : 0.f; cnt += f ? 1.f : 0.f; }
-    if (S >= 3 && K >= 3) { const bool f = m2 < PSW_INF; acc += f ? m2 : 0.f; cnt += f ? 1.f : 0.f; }
-    if (S >= 4 && K >= 4) { const bool f = m3 < PSW_INF; acc += f ? m3 : 0.f; cnt += f ? 1.f : 0.f; }
-    return (m0 < PSW_INF) ? acc * __builtin_amdgcn_rcpf(cnt) : PSW_INF;
+    // branch-free for a runtime K: the valid ones among the K best are a
+    // prefix of the sorted costs, so the weight is that of the last one
+    // added; an invalid best gives +inf by itself (inf + 0 and inf * w)
+    float acc = m0, w = 1.0f;
+    { const bool f = (K >= 2) & (m1 < PSW_INF); acc += f ? m1 : 0.f; w = f ? 0.5f : w; }
+    if (S >= 3) { const bool f = (K >= 3) & (m2 < PSW_INF); acc += f ? m2 : 0.f; w = f ? (1.0f / 3.0f) : w; }
+    if (S >= 4) { const bool f = (K >= 4) & (m3 < PSW_INF); acc += f ? m3 : 0.f; w = f ? 0.25f : w; }
+    return acc * w;
 }
 
 // Winner-take-all result of one pixel: parabolic subpixel step through the
@@ -292,10 +295,11 @@ struct Tile {
 
     static constexpr size_t lds_bytes() { return 2 * (size_t)S * T * kWave * sizeof(ST); }
 
-    __device__ static void run(const JobDev *__restrict__ Jp, int tile_x, int tile_y, int chunk, char *smem) {
+    // lane = threadIdx.x % 64 (passed in: see the persistent kernel)
+    __device__ static void run(const JobDev *__restrict__ Jp, int tile_x, int tile_y, int chunk, char *smem,
+                               const int lane) {
         const JobDev &J = *Jp;
         ST *tile = reinterpret_cast<ST *>(smem);
-        const int lane = threadIdx.x & (kWave - 1);
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
         __builtin_assume(wave >= 0 && wave < NW);   // lets the warp rows' loads issue as one batch
         const int W = J.w, H = J.h;
@@ -324,7 +328,7 @@ struct Tile {
                 av[m] = (col_in && v < H) ? Texel<IMG>::ref(J.ref, (int64_t)v * J.ref_pitch + sc) - 128.0f : 0.0f;
             }
         }
-        float mean_a[R], isd_a[R];
+        float mean_a[R], nis_a[R];   // reference window mean and -1/(2 sqrt(S_aa))
         uint32_t pos_ok = 0, ref_ok = 0;
         if constexpr (IMG == 1) {
             // float images: window sums in FP64 (products of floats are exact)
@@ -348,7 +352,7 @@ struct Tile {
                     pos_ok |= (p ? 1u : 0u) << i;
                     ref_ok |= (r ? 1u : 0u) << i;
                     mean_a[i] = (float)(sa / N);
-                    isd_a[i] = r ? __builtin_amdgcn_rsqf(var_a) : 0.0f;
+                    nis_a[i] = r ? -0.5f * __builtin_amdgcn_rsqf(var_a) : 0.0f;
                 }
             }
         } else {
@@ -374,7 +378,7 @@ struct Tile {
                     pos_ok |= (p ? 1u : 0u) << i;
                     ref_ok |= (r ? 1u : 0u) << i;
                     mean_a[i] = (float)sa / N;
-                    isd_a[i] = r ? __builtin_amdgcn_rsqf(var_a) : 0.0f;
+                    nis_a[i] = r ? -0.5f * __builtin_amdgcn_rsqf(var_a) : 0.0f;
                 }
             }
         }
@@ -524,9 +528,9 @@ struct Tile {
                             const bool bad = __builtin_amdgcn_inverse_ballot_w64(dilate<WIN>(bm));
                             const float cov = fmaf(-mean_a[i], hb, hab);
                             const float varb = fmaf(-hb * invN, hb, hbb);
-                            float zn = cov * isd_a[i] * __builtin_amdgcn_rsqf(varb);
-                            zn = __builtin_amdgcn_fmed3f(zn, -1.0f, 1.0f);
-                            const float c = fmaf(-0.5f, zn, 0.5f);
+                            // (1 - ZNCC) / 2 with ZNCC = cov / sqrt(S_aa S_bb), clamped to [0, 1]
+                            const float c = __builtin_amdgcn_fmed3f(
+                                fmaf(cov * nis_a[i], __builtin_amdgcn_rsqf(varb), 0.5f), 0.0f, 1.0f);
                             cs4[s] = (!bad && varb > vfn) ? c : PSW_INF;
                         }
                         const float C0 = aggregate<S>(cs4, K);
@@ -535,14 +539,14 @@ struct Tile {
                         if (kk == 0) cfirst[i] = C;
                         if (!SOFT) {
                             // branch-free: with c1 <= c2 (no NaN reaches here) the new
-                            // second best is med3(c1, c2, C) and the new best min(c1, C)
+                            // second best is med3(c1, c2, C)
                             const bool nb = C < c1[i];
-                            const bool fill = (kb[i] == k - 1) && (kk > 0);
+                            const bool fill = (kb[i] == k - 1) & (kk > 0);
                             cp[i] = nb ? PSW_INF : (fill ? C : cp[i]);
                             c2[i] = __builtin_amdgcn_fmed3f(c1[i], c2[i], C);
                             cm[i] = nb ? cprev[i] : cm[i];
                             kb[i] = nb ? k : kb[i];
-                            c1[i] = __builtin_amdgcn_fmed3f(c1[i], C, -PSW_INF);
+                            c1[i] = nb ? C : c1[i];
                             cprev[i] = C;
                         } else if (C < PSW_INF) {
                             const float l = -C * invT;
@@ -608,7 +612,15 @@ __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__r
     const int chunk = i / per_chunk;
     const int r = i - chunk * per_chunk;
     const int tile_y = x + 8 * (r / tx);
-    Tile<WIN, R, NW, S, STORE, SOFT, IMG>::run(job, r % tx, tile_y, chunk, smem);
+    Tile<WIN, R, NW, S, STORE, SOFT, IMG>::run(job, r % tx, tile_y, chunk, smem, threadIdx.x & (kWave - 1));
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+// threadIdx.x % 64 from an instruction the compiler may not hoist or merge
+__device__ __forceinline__ int opaque_lane() {
+    int lane;
+    asm volatile("v_and_b32 %0, 63, %1" : "=v"(lane) : "v"((int)threadIdx.x));
+    return lane;
 }
 
 // One persistent launch for every (frame, level, tile) of a run: workgroups
@@ -632,8 +644,19 @@ __global__ __launch_bounds__(kWave *NW) void sweep_persistent_kernel(const JobDe
         const int ntile = J->tiles_x * J->tiles_y;
         const int tile = t % ntile, chunk = t / ntile;
         const int tx = tile % J->tiles_x, ty = tile / J->tiles_x;
-        if (J->window == 7) Tile<7, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem);
-        else Tile<9, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem);
+        // The compiler hoists the per-lane constants of both windows' sweeps
+        // (lane-shift addresses and the like) out of this loop, where they stay
+        // live across it: about 17 VGPRs more than either sweep needs.  An
+        // opaque lane index in each branch prevents that.  It is used where it
+        // brings the kernel to 4 waves per SIMD (three sources FP32: 129 -> 125
+        // VGPRs; four sources FP16: 145 -> 128, BF16: 144 -> 126).  Elsewhere
+        // it gains no wave, and for four sources FP32 (146 -> 129, still 3
+        // waves) the batch ran 25 % slower with it.
+        constexpr bool opaque = (S == 3 && STORE == 0) || (S == 4 && STORE != 0);
+        if (J->window == 7)
+            Tile<7, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
+        else
+            Tile<9, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
     }
 }
 
