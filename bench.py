@@ -382,6 +382,89 @@ def bench_tsdf(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_filter(args):
+    """Depth-map filtering (Sec. III-A: best cost, uniqueness ratio, local
+    continuity) and box masking (Sec. IV-B) of the C2 map (1024x768, the
+    sweep's merged output).  Calls are timed back to back with HIP events on
+    the current stream.  Both kernels are HBM-bound: the filter's algorithmic
+    bytes are 17 per pixel (depth, cost1, cost2 read, kept range and code
+    written), the mask's 5 per masked pixel (range and code written).  The
+    filter codes are compared with the oracle's on the same maps."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+
+    wl = scenegen.workload("C2")
+    fr, st = wl.frames[0], wl.settings
+    W, H = fr.ref_cam.width, fr.ref_cam.height
+    ps = PlaneSweep(st, W, H, len(fr.srcs))
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    out = ps.alloc_outputs()
+    ps.run([frame_to_device(fr)], [out])
+    merged = out["merged"]
+    rng = np.random.default_rng(31)
+    boxes = [tuple(int(v) for v in (x, y, x + bw, y + bh)) for x, y, bw, bh in
+             zip(rng.integers(0, W - 200, 12), rng.integers(H // 3, H - 200, 12),
+                 rng.integers(40, 200, 12), rng.integers(40, 200, 12))]
+    mask = np.zeros((H, W), bool)
+    for x0, y0, x1, y1 in boxes:
+        mask[y0:y1, x0:x1] = True
+    n_masked = int(mask.sum())
+
+    def timed(fn, n, reps=5):
+        # n back-to-back calls between two events (the launches queue ahead
+        # of the GPU, so host submission is not inside the figure), reps times
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1) / n)
+        return ms
+
+    for _ in range(args.warmup):
+        d, c = ps.filter(merged)
+        ps.mask_boxes(d, boxes, code=c)
+    torch.cuda.synchronize()
+    f_ms = timed(lambda: ps.filter(merged), args.steps)
+    d, c = ps.filter(merged)
+    torch.cuda.synchronize()
+    gd, gc = d.cpu().numpy(), c.cpu().numpy()
+    m_ms = timed(lambda: ps.mask_boxes(d, boxes, code=c), args.steps)
+    m = {k: v.cpu().numpy() for k, v in merged.items()}
+    ps.close()
+    f_med, m_med = float(np.median(f_ms)), float(np.median(m_ms))
+    f_bytes, m_bytes = 17.0 * W * H, 5.0 * n_masked
+    line = {"metric": "depth-map filter and box mask, 1024x768 (C2 map)", "workload": "filter",
+            "filter_ms": f_med, "filter_ms_min_max": [float(min(f_ms)), float(max(f_ms))],
+            "filter_maps_per_s": 1e3 / f_med,
+            "filter_roofline": {"bound": "hbm", "achieved": f_bytes / (f_med * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                                "unit": "GB/s", "frac": f_bytes / (f_med * 1e-3) / HBM_PEAK,
+                                "algorithmic_bytes": f_bytes},
+            "mask_ms": m_med, "mask_boxes": len(boxes), "masked_pixels": n_masked,
+            "mask_roofline": {"bound": "hbm", "achieved": m_bytes / (m_med * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                              "unit": "GB/s", "frac": m_bytes / (m_med * 1e-3) / HBM_PEAK,
+                              "algorithmic_bytes": m_bytes},
+            "filter_codes": {str(k): int(v) for k, v in zip((0, 1, 2, 3, 255),
+                                                          np.bincount(gc.ravel(), minlength=256)[[0, 1, 2, 3, 255]])}}
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        od, oc = oracle.depth_filter(fr.ref_cam, st.ground_n, m["depth"].astype(np.float64),
+                                     m["cost1"].astype(np.float64), m["cost2"].astype(np.float64))
+        dt = time.perf_counter() - t0
+        near = np.abs(m["cost2"].astype(np.float64) - 1.05 * m["cost1"]) <= 1e-6 * np.abs(m["cost2"])
+        line["codes_differing_off_threshold"] = int(((gc != oc) & ~near).sum())
+        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "filtered maps/s", "cores": 1,
+                                "kind": "oracle", "sample": "the whole 1024x768 map, FP64"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -389,10 +472,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5", "paper", "tsdf"],
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5", "paper", "tsdf", "filter"],
                     help="C2 (default): the benchmark line; C3: two-level maps per staging precision; "
                          "C4: soft forward and backward; C5: batched vs plain; paper: the paper's shape "
-                         "with 5 and 3 cameras; tsdf: depth-map fusion")
+                         "with 5 and 3 cameras; tsdf: depth-map fusion; filter: depth-map filter and box mask")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -412,6 +495,9 @@ def main():
         return
     if args.workload == "tsdf":
         bench_tsdf(args)
+        return
+    if args.workload == "filter":
+        bench_filter(args)
         return
 
     import torch

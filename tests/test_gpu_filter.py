@@ -71,3 +71,32 @@ def test_mask_boxes_after_filter():
     keep = (gc == 0) & (oc == 0)
     assert np.array_equal(gd[keep], od[keep].astype(np.float32))
     assert np.all(np.isnan(gd[gc != 0]))
+
+def test_filter_c2_full_map():
+    """The filter on the full C2 map (1024x768, three sources, both plane
+    families) against the oracle's filter of the same maps."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+    wl = scenegen.workload("C2")
+    fr, st = wl.frames[0], wl.settings
+    ps = PlaneSweep(st, 1024, 768, 3)
+    ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
+    out = ps.alloc_outputs()
+    ps.run([frame_to_device(fr)], [out])
+    d, c = ps.filter(out["merged"])
+    torch.cuda.synchronize()
+    m = {k: v.cpu().numpy() for k, v in out["merged"].items()}
+    gd, gc = d.cpu().numpy(), c.cpu().numpy()
+    ps.close()
+    od, oc = oracle.depth_filter(fr.ref_cam, st.ground_n, m["depth"].astype(np.float64),
+                                 m["cost1"].astype(np.float64), m["cost2"].astype(np.float64))
+    near = np.abs(m["cost2"].astype(np.float64) - 1.05 * m["cost1"]) <= 1e-6 * np.abs(m["cost2"])
+    diff = (gc != oc) & ~near
+    counts = np.bincount(gc.ravel(), minlength=256)[[0, 1, 2, 3, 255]]
+    print("codes", counts, "mismatch", diff.sum())
+    assert diff.sum() == 0
+    assert counts[0] > 0.1 * gc.size and counts[1] > 0 and counts[3] > 0   # every filter acts
+    keep = (gc == 0) & (oc == 0)
+    assert np.array_equal(gd[keep], od[keep].astype(np.float32))
+    assert np.all(np.isnan(gd[gc != 0]))
