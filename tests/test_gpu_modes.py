@@ -2,6 +2,8 @@
 its stated bound, the batched persistent launch and its HIP graph against the
 per-level launches, and the soft-argmin forward and backward against the
 FP64 oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -83,16 +85,22 @@ def _two_level_settings(w, h):
     ], best_k=2)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_persistent_and_graph_match_grid(storage):
+@pytest.mark.parametrize("storage,n_src", [("f32", 4), ("f16", 4), ("bf16", 4), ("f32", 3)])
+def test_persistent_and_graph_match_grid(storage, n_src):
+    """Bitwise equal maps from the persistent launch, its graph replays and
+    the per-level grid launches, for every persistent kernel the batched
+    benchmarks use (three and four sources; FP32, FP16 and BF16 staging)."""
     PlaneSweep, frame_to_device = _gpu()
     sizes = [(256, 192), (200, 150), (160, 120)]
     frames = [scenegen._street_frame(w, h, 0.3516 * w, 7000 + i, 8000 + i, ss=1, extra_right=True)
               for i, (w, h) in enumerate(sizes)]
+    frames = [dataclasses.replace(f, srcs=f.srcs[:n_src], src_cams=f.src_cams[:n_src], poses=f.poses[:n_src])
+              for f in frames]
+    assert all(len(f.srcs) == n_src for f in frames)
     st = _two_level_settings(*sizes[0])
     outs = {}
     for launch in ("grid", "persistent"):
-        ps = PlaneSweep(st, 256, 192, 4, max_frames=3, max_camera_sets=3, storage=storage, launch=launch)
+        ps = PlaneSweep(st, 256, 192, n_src, max_frames=3, max_camera_sets=3, storage=storage, launch=launch)
         dev = []
         for i, (fr, (w, h)) in enumerate(zip(frames, sizes)):
             ps.set_cameras(i, fr.ref_cam, fr.src_cams, fr.poses)
