@@ -95,6 +95,27 @@ struct Shifts {
 // block sums B_n[l] = sum v[l-n+1 .. l] placed at the window's right end.
 template <int WIN, typename T, typename SHR1, typename FROM>
 __device__ __forceinline__ T window_sum(T v, const Shifts &sh, SHR1 s1, FROM from) {
+    // Windows 5, 7 and 9: the same operand pairs added in the same order as
+    // the general form below (so the same result bit for bit on the interior
+    // lanes: a + b == b + a), with two lane permutes fewer.  A block needed at
+    // one place only is added from its two halves there, shifts by one lane
+    // are DPP operands, and B4 takes B2[l-2] through two of them (lanes 0 and 1
+    // then get 0 instead of a wrapped value; no output reads them).  The
+    // ds_bpermute round trips sit on the critical path of the row loop: two
+    // fewer per sum took C2's kernel from 0.99 to 0.85 ms, although the DPP
+    // form of B4 costs two more VALU instructions.
+    if constexpr (WIN == 5) {
+        const T b2 = v + s1(v);
+        return (from(b2, sh.at(-2)) + b2) + from(v, sh.at(2));          // B4[l+2] + v[l-2]
+    } else if constexpr (WIN == 7) {
+        const T b2 = v + s1(v);
+        const T b4 = b2 + s1(s1(b2));
+        return (from(b4, sh.at(-3)) + s1(b2)) + from(v, sh.at(3));      // B4[l+3] + B2[l-1] + v[l-3]
+    } else if constexpr (WIN == 9) {
+        const T b2 = v + s1(v);
+        const T b4 = b2 + s1(s1(b2));
+        return (from(b4, sh.at(-4)) + b4) + from(v, sh.at(4));          // B8[l+4] + v[l-4]
+    }
     constexpr int h = WIN / 2;
     T b1 = v;
     T b2 = v + s1(v);
