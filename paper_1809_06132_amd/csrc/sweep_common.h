@@ -116,10 +116,14 @@ __device__ __forceinline__ T window_sum(T v, const Shifts &sh, SHR1 s1, FROM fro
         const T b4 = b2 + s1(s1(b2));
         return (from(b4, sh.at(-4)) + b4) + from(v, sh.at(4));          // B8[l+4] + v[l-4]
     }
+    // Other windows: blocks B_n[l] = sum v[l-n+1 .. l] placed at the window's
+    // right end; B4 takes B2[l-2] through two DPP shifts (lanes 0 and 1 get 0,
+    // and no output reads B4 or B8 there), a placement one lane to the left is
+    // a DPP shift, the others are lane permutes.
     constexpr int h = WIN / 2;
     T b1 = v;
     T b2 = v + s1(v);
-    T b4 = (WIN >= 5) ? b2 + from(b2, sh.at(2)) : b2;
+    T b4 = (WIN >= 5) ? b2 + s1(s1(b2)) : b2;
     T b8 = (WIN >= 9) ? b4 + from(b4, sh.at(4)) : b4;
     // the first block placed starts the sum (0 + x is not free: it turns -0
     // into +0, so the compiler keeps the add)
@@ -130,10 +134,12 @@ __device__ __forceinline__ T window_sum(T v, const Shifts &sh, SHR1 s1, FROM fro
         acc = first ? blk : acc + blk;
         first = false;
     };
-    if (WIN & 8) { put(from(b8, sh.at(-pos))); pos -= 8; }
-    if (WIN & 4) { put(from(b4, sh.at(-pos))); pos -= 4; }
-    if (WIN & 2) { put(from(b2, sh.at(-pos))); pos -= 2; }
-    if (WIN & 1) { put((pos == 0) ? b1 : from(b1, sh.at(-pos))); }
+    // the block's value at lane l + p
+    auto at_offset = [&](T blk, int p) { return p == 0 ? blk : (p == -1 ? s1(blk) : from(blk, sh.at(-p))); };
+    if (WIN & 8) { put(at_offset(b8, pos)); pos -= 8; }
+    if (WIN & 4) { put(at_offset(b4, pos)); pos -= 4; }
+    if (WIN & 2) { put(at_offset(b2, pos)); pos -= 2; }
+    if (WIN & 1) { put(at_offset(b1, pos)); }
     return acc;
 }
 template <int WIN>
