@@ -267,7 +267,11 @@ psweep_status psweep_set_chunks(psweep_ctx *ctx, int32_t level, int32_t n_chunks
 psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
                                    const psweep_output *out, void *hip_stream);
 
-/* Launch the captured graph on hip_stream.  ESTATE if none was captured. */
+/* Launch the captured graph on hip_stream.  ESTATE if none was captured.
+ * The graph writes the same frame slots of the workspace as psweep_run (its
+ * plane tables, level images and partial states), so graph launches and runs
+ * must be ordered on one stream like any two runs; the next psweep_run sets
+ * its plane tables up afresh. */
 psweep_status psweep_graph_launch(psweep_ctx *ctx, void *hip_stream);
 
 /* Record HIP events around every sweep-kernel launch of later runs (on = 1)
@@ -289,6 +293,16 @@ psweep_status psweep_sweep_kernel_times(psweep_ctx *ctx, double *ms, int32_t cap
  * psweep_run with these frames, for throughput accounting. */
 psweep_status psweep_plane_pixels(const psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
                                   int64_t *count);
+
+/* The (pixel, plane) pairs of the same run that take part in the method:
+ * pixels whose whole window lies inside their level's reference image and
+ * whose Eq. (1) ray meets the plane in front of the camera (z > 0 for a
+ * fronto plane, n . r > 0 for a ground plane; computed in FP64 on the host,
+ * O(pixels) per call).  Pairs left out have no cost at all: the ray never
+ * reaches the plane, or the pixel has no window.  For throughput accounting
+ * against the algorithmic work. */
+psweep_status psweep_plane_pixels_met(const psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                                      int64_t *count);
 
 /* Wait for the context's work, free its host state and events. */
 void psweep_destroy(psweep_ctx *ctx);

@@ -66,8 +66,12 @@ class SoftDepth(torch.autograd.Function):
         ctx.shapes = [tuple(s.shape) for s in srcs]
         ctx.float_src = [s.dtype != torch.uint8 for s in srcs]
         ctx.keep = (ref, u8)           # the backward reads these images again
+        ctx.run_id = sweep.soft_run_id
         ctx.xi_dtype, ctx.xi_device = pose_xi.dtype, pose_xi.device
         ctx.mark_non_differentiable(out["soft_lse"])
+        # the backward also reads rho and lse of this run: saved, so that the
+        # caller dropping them cannot free their memory
+        ctx.save_for_backward(out["soft_invdepth"], out["soft_lse"])
         return out["soft_invdepth"], out["soft_lse"]
 
     @staticmethod
@@ -78,7 +82,8 @@ class SoftDepth(torch.autograd.Function):
         # image gradients only for float sources that ask for them (inputs
         # 0..2 are the sweep, the reference and the pose)
         want = [f and ctx.needs_input_grad[3 + s] for s, f in enumerate(ctx.float_src)]
-        gs, gp = ctx.sweep.soft_backward(g, ctx.shapes, image_grads=want)
+        _ = ctx.saved_tensors   # rho and lse of this run, alive until the kernel has read them
+        gs, gp = ctx.sweep.soft_backward(g, ctx.shapes, image_grads=want, run_id=ctx.run_id)
         g_src = tuple(gs)
         return (None, None, gp.to(device=ctx.xi_device, dtype=ctx.xi_dtype)) + g_src
 

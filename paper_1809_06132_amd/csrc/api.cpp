@@ -5,8 +5,10 @@
 //   sweep (one grid per level, or one persistent launch) -> level merge.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -116,6 +118,8 @@ struct psweep_ctx {
     int staging_idx = 0;
     std::vector<char> last_table;
     uint64_t cam_version = 1, setup_version = 0;
+    // item orders by level geometry and launch shape (see item_order)
+    std::map<std::vector<double>, std::vector<int32_t>> order_cache;
     int tile_rows[PSWEEP_MAX_LEVELS] = {4, 4}, tile_waves[PSWEEP_MAX_LEVELS] = {4, 4};
     int chunks[PSWEEP_MAX_LEVELS] = {0, 0};   // plane chunks per tile; 0 = automatic
     int n_cu = 256;
@@ -229,9 +233,20 @@ psweep_status check_config(const psweep_config *c) {
 
 struct Blob {
     std::vector<char> bytes;
-    size_t jobs = 0, setups = 0, preps = 0, borders = 0, merges = 0;
+    size_t jobs = 0, setups = 0, preps = 0, borders = 0, merges = 0, orders = 0;
     int nj = 0, nm = 0;
 };
+
+// Largest number of (chunk, tile) items of one job on level l of a config:
+// the level's largest image, the smallest tile (4 output rows, 64 - 2 h
+// columns) and the most chunks.
+size_t max_items(const psweep_config &c, int l, int w, int h) {
+    const int hw = c.level[l].window / 2;
+    const int txo = kWave - 2 * hw;
+    const size_t tx = (size_t)std::max(0, (w - 2 * hw + txo - 1) / txo);
+    const size_t ty = (size_t)std::max(0, (h - 2 * hw + 3) / 4);
+    return tx * ty * kMaxChunks;
+}
 
 }  // namespace
 
@@ -263,12 +278,16 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
         ctx->ref_h[l] = ctx->src_h[l];
     }
     // table region: every kind of record for kMaxJobs jobs
+    size_t order_bytes = 0;
+    for (int l = 0; l < cfg->n_levels; ++l)
+        order_bytes += align_up(sizeof(int32_t) * (kQueueHead + max_items(*cfg, l, ctx->ref_w[l], ctx->ref_h[l]))) *
+                       (size_t)cfg->max_frames;
     ctx->table_bytes = align_up(sizeof(JobDev) * kMaxJobs) + align_up(sizeof(SetupDev) * kMaxJobs) +
                        align_up(sizeof(PrepDev) * kMaxJobs) + align_up(sizeof(BorderDev) * kMaxJobs) +
-                       align_up(sizeof(MergeDev) * kMaxJobs);
+                       align_up(sizeof(MergeDev) * kMaxJobs) + order_bytes;
     size_t off = 0;
     for (int g = 0; g < 2; ++g) { ctx->off_table[g] = off; off += ctx->table_bytes; }
-    for (int g = 0; g < 2; ++g) { ctx->off_counter[g] = off; off += kAlign; }
+    for (int g = 0; g < 2; ++g) { ctx->off_counter[g] = off; off += align_up(sizeof(int) * (kQueueHead + kQueues * kMaxJobs)); }
     ctx->off_slots = off;
     size_t so = 0;
     const int S = cfg->max_sources;
@@ -413,14 +432,108 @@ psweep_status psweep_plane_pixels(const psweep_ctx *ctx, const psweep_frame *fra
     return PSWEEP_OK;
 }
 
+psweep_status psweep_plane_pixels_met(const psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                                      int64_t *count) {
+    if (!ctx || !frames || !count || n_frames < 1) return PSWEEP_EINVAL;
+    const psweep_config &cfg = ctx->cfg;
+    int64_t n = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const int cs = frames[f].camera_set;
+        if (cs < 0 || cs >= (int)ctx->sets.size() || !ctx->sets[cs].defined) return PSWEEP_ESTATE;
+        const CamSet &C = ctx->sets[cs];
+        for (int l = 0; l < cfg.n_levels; ++l) {
+            const psweep_level &L = cfg.level[l];
+            int cx0 = L.crop_x, cy0 = L.crop_y, cw = L.crop_w, ch = L.crop_h;
+            if (l == 1 && C.crop_set) { cx0 = C.crop[0]; cy0 = C.crop[1]; cw = C.crop[2]; ch = C.crop[3]; }
+            const LevelCam lc = level_cam(C.ref, L.downsample, cx0, cy0, cw, ch);
+            const int hw = L.window / 2;
+            // Eq. (1): the unit ray is eta (x, y, 1 - xi / eta), so its z is
+            // eta - xi; a fronto plane (z = 1 / rho > 0) is met when that is
+            // positive, a ground plane (n . X = ground_d - h > 0) when n . r is
+            int64_t met_f = 0, met_g = 0;
+            for (int j = hw; j < lc.h - hw; ++j) {
+                const double y = (j - lc.cy) / lc.fy;
+                for (int i = hw; i < lc.w - hw; ++i) {
+                    const double x = (i - lc.cx) / lc.fx;
+                    const double q = x * x + y * y;
+                    const double eta = (lc.xi + std::sqrt(1.0 + (1.0 - lc.xi * lc.xi) * q)) / (q + 1.0);
+                    const double rz = eta - lc.xi;
+                    met_f += rz > 0.0;
+                    met_g += cfg.ground_n[0] * eta * x + cfg.ground_n[1] * eta * y + cfg.ground_n[2] * rz > 0.0;
+                }
+            }
+            n += met_f * L.n_fronto + met_g * L.n_ground;
+        }
+    }
+    *count = n;
+    return PSWEEP_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
+// The item queues of one job (see JobDev::order): tile row y goes to queue
+// y mod 8, one queue per XCD, so that an XCD's L2 holds the source texels of
+// its rows; each queue is sorted largest item first, the size of an item
+// being its (pixel, plane) pairs that meet their plane (the pixels of its
+// tile whose Eq. (1) ray meets the chunk's family, times the chunk's planes;
+// FP64 on the host).  Long items then start first and short ones fill the
+// end of the launch, instead of a long one starting last; ties keep the
+// chunk-major order.  Depends only on the level's geometry and the launch
+// shape: cached.
+const std::vector<int32_t> &item_order(psweep_ctx *ctx, const LevelCam &rc, const psweep_level &L,
+                                       const JobDev &J) {
+    const psweep_config &cfg = ctx->cfg;
+    const std::vector<double> key = {rc.xi, rc.fx, rc.fy, rc.cx, rc.cy, (double)rc.w, (double)rc.h,
+                                     (double)L.window, (double)L.n_fronto, (double)L.n_ground,
+                                     cfg.ground_n[0], cfg.ground_n[1], cfg.ground_n[2], (double)J.rows,
+                                     (double)J.waves, (double)J.nch_f, (double)J.nch_g};
+    auto it = ctx->order_cache.find(key);
+    if (it != ctx->order_cache.end()) return it->second;
+    const int hw = L.window / 2, txo = kWave - 2 * hw, tyo = J.rows * J.waves;
+    const int ntile = J.tiles_x * J.tiles_y;
+    std::vector<int64_t> met_f(ntile, 0), met_g(ntile, 0);
+    for (int j = hw; j < rc.h - hw; ++j) {
+        const double y = (j - rc.cy) / rc.fy;
+        const int trow = ((j - hw) / tyo) * J.tiles_x;
+        for (int i = hw; i < rc.w - hw; ++i) {
+            const double x = (i - rc.cx) / rc.fx;
+            const double q = x * x + y * y;
+            const double eta = (rc.xi + std::sqrt(1.0 + (1.0 - rc.xi * rc.xi) * q)) / (q + 1.0);
+            const double rz = eta - rc.xi;
+            const int t = trow + (i - hw) / txo;
+            met_f[t] += rz > 0.0;
+            met_g[t] += cfg.ground_n[0] * eta * x + cfg.ground_n[1] * eta * y + cfg.ground_n[2] * rz > 0.0;
+        }
+    }
+    const int nch = std::max(1, J.nch_f + J.nch_g);
+    std::vector<int64_t> weight((size_t)nch * ntile);
+    for (int c = 0; c < nch; ++c) {
+        int kb = 0, ke = L.n_fronto + L.n_ground;
+        if (nch > 1) chunk_range(L.n_fronto, L.n_ground, J.nch_f, J.nch_g, c, &kb, &ke);
+        const int64_t pf = std::max(0, std::min(ke, L.n_fronto) - kb);
+        const int64_t pg = std::max(0, ke - std::max(kb, L.n_fronto));
+        for (int t = 0; t < ntile; ++t) weight[(size_t)c * ntile + t] = met_f[t] * pf + met_g[t] * pg;
+    }
+    std::vector<int32_t> order(kQueueHead, 0);
+    for (int q = 0; q < kQueues; ++q) {
+        order[q] = (int32_t)(order.size() - kQueueHead);
+        const size_t lo = order.size();
+        for (int c = 0; c < nch; ++c)
+            for (int y = q; y < J.tiles_y; y += kQueues)
+                for (int x = 0; x < J.tiles_x; ++x) order.push_back(c * ntile + y * J.tiles_x + x);
+        std::stable_sort(order.begin() + lo, order.end(), [&](int32_t a, int32_t b) { return weight[a] > weight[b]; });
+    }
+    order[kQueues] = (int32_t)(order.size() - kQueueHead);
+    return ctx->order_cache.emplace(key, std::move(order)).first->second;
+}
+
 // Build the per-run tables (host side) for `frames`: job, setup, prep,
-// border and merge records packed at fixed offsets of one blob.
+// border and merge records and the jobs' item orders, packed at fixed
+// offsets of one blob that is uploaded to device address `tb`.
 psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, const psweep_output *out,
-                           Blob &blob, std::vector<int> &job_frame) {
+                           char *tb, int *counters, Blob &blob, std::vector<int> &job_frame) {
     const psweep_config &cfg = ctx->cfg;
     const int NL = cfg.n_levels;
     const bool sf = single_full(cfg);
@@ -429,6 +542,8 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
     std::vector<PrepDev> preps;
     std::vector<BorderDev> borders;
     std::vector<MergeDev> merges;
+    std::vector<const std::vector<int32_t> *> orders;   // map nodes: stable while the run is built
+    if (ctx->order_cache.size() > 192) ctx->order_cache.clear();   // one run adds at most kMaxJobs
     int first_item = 0;
     for (int f = 0; f < nf; ++f) {
         const psweep_frame &fr = frames[f];
@@ -548,6 +663,8 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
                 const int items = ntile * std::max(1, J.nch_f + J.nch_g);
                 J.first_item = first_item;
                 first_item += items;
+                orders.push_back(&item_order(ctx, rc, L, J));
+                J.queue_ctr = counters + kQueueHead + kQueues * (int)orders.size() - kQueues;
             }
             for (int s = 0; s < C.n_src; ++s) {
                 const LevelCam sc = level_cam(C.src[s], ds, 0, 0, 0, 0);
@@ -635,9 +752,17 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
     blob.preps = blob.setups + align_up(sizeof(SetupDev) * nj);
     blob.borders = blob.preps + align_up(sizeof(PrepDev) * nj);
     blob.merges = blob.borders + align_up(sizeof(BorderDev) * nj);
-    const size_t total = blob.merges + align_up(sizeof(MergeDev) * (nm > 0 ? nm : 1));
+    blob.orders = blob.merges + align_up(sizeof(MergeDev) * (nm > 0 ? nm : 1));
+    size_t total = blob.orders;
+    for (int j = 0; j < nj; ++j) {
+        jobs[j].order = (const int32_t *)(tb + total);
+        total += align_up(sizeof(int32_t) * orders[j]->size());
+    }
     if (total > ctx->table_bytes) return fail(ctx, PSWEEP_EINVAL, "too many frames for the table region");
     blob.bytes.assign(total, 0);
+    for (int j = 0; j < nj; ++j)
+        std::memcpy(blob.bytes.data() + ((const char *)jobs[j].order - tb), orders[j]->data(),
+                    sizeof(int32_t) * orders[j]->size());
     std::memcpy(blob.bytes.data() + blob.jobs, jobs.data(), sizeof(JobDev) * nj);
     std::memcpy(blob.bytes.data() + blob.setups, setups.data(), sizeof(SetupDev) * nj);
     std::memcpy(blob.bytes.data() + blob.preps, preps.data(), sizeof(PrepDev) * nj);
@@ -672,6 +797,14 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
         PSW_HIP(hipLaunchKernel(psw_prep_kernel(), dim3(256, 1 + maxS, nj), dim3(256), a, 0, stream), "prep");
     }
     const int store = cfg.storage, soft = cfg.mode == PSWEEP_MODE_SOFT ? 1 : 0;
+    {
+        // the item queues' take counters of every job start at zero (a kernel,
+        // not a memset: the run may be captured into a graph)
+        int *counter = (int *)(ctx->ws + ctx->off_counter[which]);
+        int n = kQueueHead + kQueues * nj;
+        void *a[] = {&counter, &n};
+        PSW_HIP(hipLaunchKernel(psw_reset_kernel(), dim3(1), dim3(256), a, 0, stream), "reset");
+    }
     if (timed) {
         const size_t need = cfg.launch == PSWEEP_LAUNCH_PERSISTENT ? 1 : (size_t)nj;
         while (ctx->ev0.size() < need) {
@@ -692,8 +825,8 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
             if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no kernel for this window/tile/sources/storage");
             JobDev *jp = dj + j;
             void *a[] = {&jp};
-            // blocks x, x + 8, ... sweep tile rows x, x + 8, ... chunk by chunk
-            const int grid = 8 * ((J.tiles_y + 7) / 8) * J.tiles_x * std::max(1, J.nch_f + J.nch_g);
+            // one block per (chunk, tile) item
+            const int grid = ntile * std::max(1, J.nch_f + J.nch_g);
             if (timed) PSW_HIP(hipEventRecord(ctx->ev0[ctx->n_timed], stream), "event record");
             PSW_HIP(hipLaunchKernel(e->fn, dim3(grid), dim3(kWave * J.waves), a, e->lds, stream), "sweep");
             if (timed) PSW_HIP(hipEventRecord(ctx->ev1[ctx->n_timed++], stream), "event record");
@@ -710,10 +843,6 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
         const KernelEntry *e = find_kernel(0, ctx->tile_rows[0], ctx->tile_waves[0], n_src, store, 0, 1, 0);
         if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no persistent kernel for this tile/sources/storage");
         int *counter = (int *)(ctx->ws + ctx->off_counter[which]);
-        {
-            void *a[] = {&counter};
-            PSW_HIP(hipLaunchKernel(psw_reset_kernel(), dim3(1), dim3(64), a, 0, stream), "reset");
-        }
         int dev = 0, n_cu = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;
@@ -771,7 +900,8 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
     Blob blob;
     std::vector<int> job_frame;
     char *tb = ctx->ws + ctx->off_table[0];
-    psweep_status st = build_tables(ctx, frames, n_frames, out, blob, job_frame);
+    psweep_status st =
+        build_tables(ctx, frames, n_frames, out, tb, (int *)(ctx->ws + ctx->off_counter[0]), blob, job_frame);
     if (st != PSWEEP_OK) return st;
     std::vector<JobDev> hj(blob.nj);
     std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);
@@ -856,7 +986,8 @@ psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, 
     Blob blob;
     std::vector<int> job_frame;
     char *tb = ctx->ws + ctx->off_table[1];
-    psweep_status st = build_tables(ctx, frames, n_frames, out, blob, job_frame);
+    psweep_status st =
+        build_tables(ctx, frames, n_frames, out, tb, (int *)(ctx->ws + ctx->off_counter[1]), blob, job_frame);
     if (st != PSWEEP_OK) return st;
     std::vector<JobDev> hj(blob.nj);
     std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);
@@ -873,6 +1004,7 @@ psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, 
     ctx->graph = g;
     PSW_HIP(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0), "graph instantiate");
     ctx->soft_ready = false;
+    ctx->setup_version = 0;
     return PSWEEP_OK;
 }
 
@@ -880,6 +1012,9 @@ psweep_status psweep_graph_launch(psweep_ctx *ctx, void *hip_stream) {
     if (!ctx) return PSWEEP_EINVAL;
     if (!ctx->gexec) return fail(ctx, PSWEEP_ESTATE, "no captured graph");
     PSW_HIP(hipGraphLaunch(ctx->gexec, (hipStream_t)hip_stream), "graph launch");
+    // the graph's setup kernel rewrote the frame slots' plane tables with the
+    // graph's own camera sets: the next psweep_run must set them up again
+    ctx->setup_version = 0;
     return PSWEEP_OK;
 }
 

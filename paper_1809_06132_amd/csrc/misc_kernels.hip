@@ -166,8 +166,8 @@ __global__ void prep_kernel(const PrepDev *__restrict__ preps, const BorderDev *
     }
 }
 
-__global__ void reset_counter_kernel(int *counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+__global__ void reset_counter_kernel(int *counter, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counter[i] = 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -54,9 +54,17 @@ struct JobDev {
     // chunk_merge_kernel combines
     int32_t nch_f, nch_g, pad3, pad4;
     float *part;           // [chunk][word][h][w], pitch w
+    // The job's (chunk, tile) items (chunk * tiles + tile) in eight queues,
+    // one per XCD: order[0 .. 8] are the queues' starts in order + kQueueHead
+    // (order[8]: the item count), each queue sorted largest item first;
+    // queue_ctr: the eight queues' take counters (zeroed before the launch).
+    const int32_t *order;
+    int32_t *queue_ctr;
     SrcDev src[kMaxSrc];
 };
 
+constexpr int kQueueHead = 16;   // ints before the items of an order table
+constexpr int kQueues = 8;       // one item queue per XCD
 constexpr int kPartWords = 7;   // c1, kb, c2, cm, cp, first, last (soft: max, sum, sum*theta)
 constexpr int kMaxChunks = 8;
 

@@ -39,24 +39,33 @@ namespace psw {
 // ---------------------------------------------------------------------------
 // staging precision of warped samples (centred: b - 128)
 // ---------------------------------------------------------------------------
+// put() stages a usable sample and never yields -0.0, the marker of an
+// unusable one (bad()).
 template <int STORE> struct Stage;
 template <> struct Stage<0> {
     using T = float;
+    // a bilinear blend of integer coefficients is never -0.0 in FP32
     static __device__ __forceinline__ T put(float v) { return v; }
+    static __device__ __forceinline__ T bad() { return -0.0f; }
     static __device__ __forceinline__ float get(T v) { return v; }
 };
 template <> struct Stage<1> {
     using T = _Float16;
-    static __device__ __forceinline__ T put(float v) { return (_Float16)v; }
+    // a tiny negative rounding residue (|v| < 2^-25) rounds to -0.0 in FP16;
+    // + 0 turns it into +0 and leaves every other value as it is
+    static __device__ __forceinline__ T put(float v) { return (_Float16)v + (_Float16)0.0f; }
+    static __device__ __forceinline__ T bad() { return (_Float16)-0.0f; }
     static __device__ __forceinline__ float get(T v) { return (float)v; }
 };
 template <> struct Stage<2> {
     using T = uint16_t;   // bfloat16 bits, round to nearest even
+    // BF16 keeps FP32's exponent range: a nonzero value stays nonzero
     static __device__ __forceinline__ T put(float v) {
         uint32_t u = __float_as_uint(v);
         u += 0x7fffu + ((u >> 16) & 1u);
         return (uint16_t)(u >> 16);
     }
+    static __device__ __forceinline__ T bad() { return (uint16_t)0x8000u; }
     static __device__ __forceinline__ float get(T v) { return __uint_as_float(((uint32_t)v) << 16); }
 };
 
@@ -68,16 +77,36 @@ template <typename T> __device__ __forceinline__ const PSW_GLOBAL T *gptr(const 
 template <typename T> __device__ __forceinline__ const PSW_CONST T *cptr(const T *p) { return (const PSW_CONST T *)p; }
 
 __device__ __forceinline__ bool is_neg_zero(float v) { return __float_as_uint(v) == 0x80000000u; }
+// Lane selects on a scalar lane mask (lane in m ? t : f), one v_cndmask
+// each.  Written as instructions because the compiler turns a group of
+// selects on one condition into an exec-masked branch with register copies.
+__device__ __forceinline__ float vsel(uint64_t m, float t, float f) {
+    return __builtin_amdgcn_inverse_ballot_w64(m) ? t : f;
+}
+__device__ __forceinline__ int vsel_i(uint64_t m, int t, int f) {
+    return __builtin_amdgcn_inverse_ballot_w64(m) ? t : f;
+}
+// lanes where a < b (ordered), as a scalar lane mask
+__device__ __forceinline__ uint64_t lanes_lt(float a, float b) {
+    return __builtin_amdgcn_fcmpf(a, b, 4 /* ordered less than */);
+}
+// the wave's lanes holding -0.0, as one compare into a scalar register pair
+// (a ballot of is_neg_zero would first be widened into a vector register)
+__device__ __forceinline__ uint64_t neg_zero_mask(float v) {
+    return __builtin_amdgcn_uicmp(__float_as_uint(v), 0x80000000u, 32 /* equal */);
+}
 
 // value of v held by lane (lane - d); lanes wrap (only interior lanes are used)
 __device__ __forceinline__ float lane_from(float v, int addr) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 __device__ __forceinline__ int lane_from_i(int v, int addr) { return __builtin_amdgcn_ds_bpermute(addr, v); }
-__device__ __forceinline__ float shr1(float v) {   // lane l gets v[l-1] (lane 0 keeps 0)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+// lane l gets v[l-1], lane 0 gets 0 (bound_ctrl: a lane with no source lane
+// reads 0, so no register has to be cleared first)
+__device__ __forceinline__ float shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
-__device__ __forceinline__ int shr1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int shr1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
 
 // Byte addresses for ds_bpermute: lane (lane - d) for the shifts a window
 // sum of side WIN needs (d = 2, 4 for the block sums, then the final
@@ -214,12 +243,18 @@ struct Texel<1> {
     }
 };
 
-// lanes whose window [l-h, l+h] contains a lane with bit set in m
+// lanes whose window [l-h, l+h] contains a lane with bit set in m (scalar
+// work): the reach grows 0 -> 1 -> 3 -> 7 by shifts of 1, 2, 4, capped at h,
+// so h = 4 takes three steps instead of four
 template <int WIN>
 __device__ __forceinline__ uint64_t dilate(uint64_t m) {
     uint64_t d = m;
+    int reach = 0;
 #pragma unroll
-    for (int s = 1; s <= WIN / 2; ++s) d |= (m << s) | (m >> s);
+    for (int step = 0; step < 4; ++step) {
+        const int k = (reach + 1 < WIN / 2 - reach) ? reach + 1 : WIN / 2 - reach;
+        if (k > 0) { d |= (d << k) | (d >> k); reach += k; }
+    }
     return d;
 }
 
@@ -262,6 +297,28 @@ __device__ __forceinline__ float aggregate(const float c[4], int K) {
     if (S >= 3) { const bool f = (K >= 3) & (m2 < PSW_INF); acc += f ? m2 : 0.f; w = f ? (1.0f / 3.0f) : w; }
     if (S >= 4) { const bool f = (K >= 4) & (m3 < PSW_INF); acc += f ? m3 : 0.f; w = f ? 0.25f : w; }
     return acc * w;
+}
+
+// Mean of the two smallest valid costs (the smallest alone if only one is
+// valid), +inf if none is: aggregate<S>(c, 2) with fewer instructions and
+// the same result (the same sum, times 0.5 or 1).
+template <int S>
+__device__ __forceinline__ float aggregate2(const float c[4]) {
+    float m0, m1;
+    if (S == 1) {
+        return c[0];
+    } else if (S == 2) {
+        m0 = fminf(c[0], c[1]); m1 = fmaxf(c[0], c[1]);
+    } else if (S == 3) {
+        m0 = __builtin_fminf(c[0], __builtin_fminf(c[1], c[2]));
+        m1 = __builtin_amdgcn_fmed3f(c[0], c[1], c[2]);
+    } else {
+        const float a0 = fminf(c[0], c[1]), a1 = fmaxf(c[0], c[1]);
+        const float a2 = fminf(c[2], c[3]), a3 = fmaxf(c[2], c[3]);
+        m0 = fminf(a0, a2);
+        m1 = fminf(fmaxf(a0, a2), fminf(a1, a3));
+    }
+    return m1 < PSW_INF ? (m0 + m1) * 0.5f : m0;
 }
 
 // Winner-take-all result of one pixel: parabolic subpixel step through the
@@ -309,7 +366,7 @@ __device__ __forceinline__ void finish_soft(const JobDev &J, int orow, int col, 
 // ---------------------------------------------------------------------------
 // the sweep of one tile
 // ---------------------------------------------------------------------------
-template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0>
+template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0, bool K2 = false>
 struct Tile {
     static constexpr int HW = WIN / 2;
     static constexpr int TXO = kWave - 2 * HW;       // output columns per tile
@@ -410,6 +467,17 @@ struct Tile {
             }
         }
 
+        // lanes of each output row without a usable reference window (outside
+        // the image, or textureless): a scalar mask, ORed into every source's
+        // unusable-window mask
+        // (Four sources leave no scalar registers for these masks: there the
+        // test is a select on the aggregated cost, and the previous plane's
+        // win is a compare of the winning index.)
+        constexpr bool kScalarMasks = S <= 3;
+        uint64_t ref_bad[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) ref_bad[i] = kScalarMasks ? __builtin_amdgcn_ballot_w64(!((ref_ok >> i) & 1u)) : 0;
+
         // --- per-pixel sweep state -------------------------------------------
         float c1[R], c2[R], cm[R], cp[R], cprev[R];
         int kb[R];
@@ -426,6 +494,7 @@ struct Tile {
         }
 
         const int K = J.best_k;
+        const float inf = PSW_INF;
         const float invN = 1.0f / (float)(WIN * WIN);
         const float vfn = J.var_floor_n;
 
@@ -450,18 +519,30 @@ struct Tile {
             // family ray parameter: tau where the family's planes are hit in
             // front of the camera, NaN elsewhere (NaN fails every later test)
             float tf[NWR];
-            bool any = false;
 #pragma unroll
             for (int i = 0; i < NWR; ++i) {
                 float t = ray_tau(x, yw[i], xi, nullptr);
                 const float g = fam ? fmaf(J.gn[0], x, fmaf(J.gn[1], yw[i], J.gn[2] * t)) : t;
-                const bool ok = g > 0.0f;
-                tf[i] = ok ? t : __builtin_nanf("");
-                any |= ok && (wave + NW * i) < T;
+                tf[i] = g > 0.0f ? t : __builtin_nanf("");
             }
-            if (!__syncthreads_or(any)) continue;
+            // A wave whose output pixels all lack a usable reference window or
+            // a ray that meets this family's planes has nothing to compute: its
+            // costs would all be unusable and leave its state as it is.  It
+            // still warps its share of the tile's rows for the others, unless
+            // no wave of the tile is live, when the tile skips the family.
+            bool live = false;
 #pragma unroll
-            for (int i = 0; i < R; ++i) cprev[i] = PSW_INF;
+            for (int i = 0; i < R; ++i) {
+                const float yo = ((float)(or0 + i) - J.cy) * J.inv_fy;
+                const float t = ray_tau(x, yo, xi, nullptr);
+                const float g = fam ? fmaf(J.gn[0], x, fmaf(J.gn[1], yo, J.gn[2] * t)) : t;
+                live |= ((ref_ok >> i) & 1u) && g > 0.0f;
+            }
+            const bool wave_live = __builtin_amdgcn_ballot_w64(live) != 0;
+            if (!__syncthreads_or(wave_live)) continue;
+            uint64_t won[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) { cprev[i] = PSW_INF; won[i] = 0; }
 
             // double-buffered tile: the warp of plane k + 1 goes to the other
             // buffer while the rows of plane k are read; one barrier per plane
@@ -503,7 +584,7 @@ struct Tile {
                         const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                         const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
                         const float b = Texel<IMG>::sample(rs, off, al, be);
-                        dst[(size_t)j * kWave] = St::put(ok ? b : -0.0f);
+                        dst[(size_t)j * kWave] = ok ? St::put(b) : St::bad();
                     }
                 }
             };
@@ -513,11 +594,18 @@ struct Tile {
                 const int k = k0 + kk;
                 const ST *cur = tile + (size_t)(kk & 1) * S * T * kWave;
                 if (kk + 1 < np) warp_plane(k + 1, tile + (size_t)((kk + 1) & 1) * S * T * kWave);
+                if (wave_live) {
                 // ---- run down the rows: vertical sums, then window sums ----
+                // Unusable samples: the compare of each row gives the wave's
+                // 64-bit mask of them (scalar registers); the rows of an output
+                // row's window are ORed on the scalar unit.  With R <= WIN the
+                // windows of the wave's R output rows share the rows R-1 ..
+                // WIN-1 (core); output i adds the rows i .. R-2 above them
+                // (head) and WIN .. i+WIN-1 below them (tail).
                 float vb[S], vbb[S], vab[S];
-                int last_bad[S];
+                uint64_t rbad[S][VR], head[S][R], core[S], tail[S];
 #pragma unroll
-                for (int s = 0; s < S; ++s) { vb[s] = 0.f; vbb[s] = 0.f; vab[s] = 0.f; last_bad[s] = -1000; }
+                for (int s = 0; s < S; ++s) { vb[s] = 0.f; vbb[s] = 0.f; vab[s] = 0.f; core[s] = 0; tail[s] = 0; }
                 const ST *col = cur + (size_t)(wave * R) * kWave + lane;
 #pragma unroll
                 for (int m = 0; m < VR; ++m) {
@@ -525,7 +613,18 @@ struct Tile {
                     for (int s = 0; s < S; ++s) {
                         const ST *cs = col + (size_t)s * T * kWave;
                         const float b = St::get(cs[(size_t)m * kWave]);
-                        last_bad[s] = is_neg_zero(b) ? m : last_bad[s];
+                        rbad[s][m] = neg_zero_mask(b);
+                        if (R <= WIN) {
+                            if (m == R - 2) {
+                                head[s][m] = rbad[s][m];
+#pragma unroll
+                                for (int r = R - 3; r >= 0; --r) head[s][r] = rbad[s][r] | head[s][r + 1];
+                            }
+                            if (m == R - 1) core[s] = rbad[s][m];
+                            else if (m > R - 1 && m < WIN) core[s] |= rbad[s][m];
+                            if (m == WIN) tail[s] = rbad[s][m];
+                            else if (m > WIN) tail[s] |= rbad[s][m];
+                        }
                         if (m == 0) {   // start the sums with the first row (no 0 + x)
                             vb[s] = b; vbb[s] = b * b; vab[s] = av[m] * b;
                         } else {
@@ -550,31 +649,47 @@ struct Tile {
                             const float hb = wsum<WIN>(vb[s], sh);
                             const float hbb = wsum<WIN>(vbb[s], sh);
                             const float hab = wsum<WIN>(vab[s], sh);
-                            // scalar work only, no branch: an empty ballot dilates to 0
-                            const uint64_t bm = __builtin_amdgcn_ballot_w64(last_bad[s] > m - WIN);
-                            const bool bad = __builtin_amdgcn_inverse_ballot_w64(dilate<WIN>(bm));
+                            // scalar work only, no branch: an empty mask dilates to 0
+                            uint64_t bm;
+                            if (R <= WIN) {
+                                bm = core[s];
+                                if (i <= R - 2) bm |= head[s][i];
+                                if (i >= 1) bm |= tail[s];
+                            } else {
+                                bm = rbad[s][i];
+#pragma unroll
+                                for (int r = 1; r < WIN; ++r) bm |= rbad[s][i + r];
+                            }
+                            if (kScalarMasks) bm = dilate<WIN>(bm) | ref_bad[i];
+                            else bm = dilate<WIN>(bm);
+                            const bool bad = __builtin_amdgcn_inverse_ballot_w64(bm);
                             const float cov = fmaf(-mean_a[i], hb, hab);
                             const float varb = fmaf(-hb * invN, hb, hbb);
                             // (1 - ZNCC) / 2 with ZNCC = cov / sqrt(S_aa S_bb), clamped to [0, 1]
                             const float c = __builtin_amdgcn_fmed3f(
                                 fmaf(cov * nis_a[i], __builtin_amdgcn_rsqf(varb), 0.5f), 0.0f, 1.0f);
-                            cs4[s] = (!bad && varb > vfn) ? c : PSW_INF;
+                            cs4[s] = (!bad && varb > vfn) ? c : PSW_INF;   // the reference window's test is in bm
                         }
-                        const float C0 = aggregate<S>(cs4, K);
-                        float C = C0;
-                        C = ((ref_ok >> i) & 1u) ? C : PSW_INF;
+                        // mean of the best K (K2: K is 2, the short form with the
+                        // same result)
+                        float C = K2 ? aggregate2<S>(cs4) : aggregate<S>(cs4, K);
+                        if (!kScalarMasks) C = ((ref_ok >> i) & 1u) ? C : PSW_INF;
                         if (kk == 0) cfirst[i] = C;
                         if (!SOFT) {
                             // branch-free: with c1 <= c2 (no NaN reaches here) the new
-                            // second best is med3(c1, c2, C)
-                            const bool nb = C < c1[i];
-                            const bool fill = (kb[i] == k - 1) & (kk > 0);
-                            cp[i] = nb ? PSW_INF : (fill ? C : cp[i]);
+                            // second best is med3(c1, c2, C) and the new best min(c1, C);
+                            // won[i] (a lane mask) says the best is the previous plane,
+                            // whose neighbour cost on the right is this plane's
+                            const uint64_t nb = lanes_lt(C, c1[i]);
+                            const uint64_t prev_won =
+                                kScalarMasks ? won[i] : (kk > 0 ? __builtin_amdgcn_ballot_w64(kb[i] == k - 1) : 0);
+                            cp[i] = vsel(nb, inf, vsel(prev_won, C, cp[i]));
                             c2[i] = __builtin_amdgcn_fmed3f(c1[i], c2[i], C);
-                            cm[i] = nb ? cprev[i] : cm[i];
-                            kb[i] = nb ? k : kb[i];
-                            c1[i] = nb ? C : c1[i];
+                            cm[i] = vsel(nb, cprev[i], cm[i]);
+                            kb[i] = vsel_i(nb, k, kb[i]);
+                            c1[i] = fminf(c1[i], C);
                             cprev[i] = C;
+                            if (kScalarMasks) won[i] = nb;
                         } else if (C < PSW_INF) {
                             const float l = -C * invT;
                             const float nm = fmaxf(c1[i], l);
@@ -586,6 +701,7 @@ struct Tile {
                         }
                     }
                 }
+                }   // wave_live
                 __syncthreads();
             }
         }
@@ -620,26 +736,44 @@ struct Tile {
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
-// One grid per (frame, level).  Workgroups go to the eight XCDs in turn
-// (block b to XCD b % 8), so XCD x runs blocks x, x + 8, ...: it is given the
-// tile rows x, x + 8, x + 16, ... of the image and sweeps them one plane
-// chunk after another.  Every XCD so holds an equal share of the image's
-// upper and lower parts (ground-plane chunks cost little above the horizon),
-// and its resident workgroups sweep the same planes over nearby tiles.
+// One grid per (frame, level), one workgroup per (chunk, tile) item, in the
+// job's item order (largest first).
 template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0>
 __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__restrict__ job) {
     extern __shared__ char smem[];
-    const int nch = job->nch_f + job->nch_g;
-    const int nc = nch > 1 ? nch : 1;
-    const int tx = job->tiles_x, ty = job->tiles_y;
-    const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
-    const int nrows = ty > x ? (ty - x + 7) / 8 : 0;     // tile rows of XCD x
-    const int per_chunk = nrows * tx;
-    if (i >= per_chunk * nc) return;
-    const int chunk = i / per_chunk;
-    const int r = i - chunk * per_chunk;
-    const int tile_y = x + 8 * (r / tx);
-    Tile<WIN, R, NW, S, STORE, SOFT, IMG>::run(job, r % tx, tile_y, chunk, smem, threadIdx.x & (kWave - 1));
+    const int tx = job->tiles_x;
+    // Blocks go to the eight XCDs round-robin (block b to XCD b % 8), and
+    // every XCD has a queue of items (its share of the tile rows, so that
+    // its L2 holds the source texels those rows reach; largest item first).
+    // A block takes the next item of its XCD's queue, or of the next queue
+    // that has items left when its own is empty, so the XCDs finish together.
+    // There are as many blocks as items: every block takes exactly one.
+    __shared__ int item_s;
+    if (threadIdx.x == 0) {
+        const PSW_CONST int32_t *hd = cptr(job->order);
+        int it = -1;
+        for (int a = 0; a < kQueues && it < 0; ++a) {
+            const int q = (blockIdx.x + a) & (kQueues - 1);
+            const int lo = hd[q], n = hd[q + 1] - lo;
+            if (n <= 0) continue;
+            const int c = atomicAdd(job->queue_ctr + q, 1);
+            if (c < n) it = hd[kQueueHead + lo + c];
+        }
+        item_s = it;
+    }
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(item_s);   // uniform: the tile stays scalar
+    if (item < 0) return;
+    const int ntile = tx * job->tiles_y;
+    const int chunk = item / ntile;
+    const int tile = item - chunk * ntile;
+    const int tile_y = tile / tx;
+    const int r = tile - tile_y * tx;
+    // the mean of the best two sources (the usual setting) has a short form
+    if (!SOFT && S >= 2 && job->best_k == 2)
+        Tile<WIN, R, NW, S, STORE, SOFT, IMG, true>::run(job, r % tx, tile_y, chunk, smem, threadIdx.x & (kWave - 1));
+    else
+        Tile<WIN, R, NW, S, STORE, SOFT, IMG>::run(job, r % tx, tile_y, chunk, smem, threadIdx.x & (kWave - 1));
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
@@ -651,23 +785,41 @@ __device__ __forceinline__ int opaque_lane() {
 }
 
 // One persistent launch for every (frame, level, tile) of a run: workgroups
-// take tiles from a global counter until all are done (every workgroup
-// leaves once the counter passes n_items).
+// take (chunk, tile) items job after job, from their XCD's queue of the job
+// (or the next queue with items left), until every job is exhausted; every
+// workgroup then leaves.
 template <int R, int NW, int S, int STORE>
 __global__ __launch_bounds__(kWave *NW) void sweep_persistent_kernel(const JobDev *__restrict__ jobs, int n_jobs,
                                                                      int n_items, int *counter) {
     extern __shared__ char smem[];
-    __shared__ int item_s;
+    __shared__ int item_s, job_s;
+    (void)n_items;
+    (void)counter;
+    int j = 0;
     for (;;) {
-        if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (j < n_jobs && it < 0) {
+                const PSW_CONST int32_t *hd = cptr(jobs[j].order);
+                for (int a = 0; a < kQueues && it < 0; ++a) {
+                    const int q = (blockIdx.x + a) & (kQueues - 1);
+                    const int lo = hd[q], n = hd[q + 1] - lo;
+                    if (n <= 0) continue;
+                    const int c = atomicAdd(jobs[j].queue_ctr + q, 1);
+                    if (c < n) it = hd[kQueueHead + lo + c];
+                }
+                if (it < 0) ++j;
+            }
+            item_s = it;
+            job_s = j;
+        }
         __syncthreads();
-        const int item = item_s;
+        // the same for every lane: uniform, so the tile's values stay scalar
+        const int t = __builtin_amdgcn_readfirstlane(item_s);
+        j = __builtin_amdgcn_readfirstlane(job_s);
         __syncthreads();
-        if (item >= n_items) break;
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].first_item <= item) ++j;
+        if (t < 0) break;
         const JobDev *J = jobs + j;
-        const int t = item - J->first_item;
         const int ntile = J->tiles_x * J->tiles_y;
         const int tile = t % ntile, chunk = t / ntile;
         const int tx = tile % J->tiles_x, ty = tile / J->tiles_x;
@@ -680,10 +832,14 @@ __global__ __launch_bounds__(kWave *NW) void sweep_persistent_kernel(const JobDe
         // it gains no wave, and for four sources FP32 (146 -> 129, still 3
         // waves) the batch ran 25 % slower with it.
         constexpr bool opaque = (S == 3 && STORE == 0) || (S == 4 && STORE != 0);
-        if (J->window == 7)
-            Tile<7, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
-        else
-            Tile<9, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
+        const bool k2 = S >= 2 && J->best_k == 2;
+        if (J->window == 7) {
+            if (k2) Tile<7, R, NW, S, STORE, false, 0, true>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
+            else Tile<7, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
+        } else {
+            if (k2) Tile<9, R, NW, S, STORE, false, 0, true>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
+            else Tile<9, R, NW, S, STORE, false>::run(J, tx, ty, chunk, smem, opaque ? opaque_lane() : lane_id());
+        }
     }
 }
 

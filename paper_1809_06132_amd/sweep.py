@@ -218,10 +218,13 @@ class PlaneSweep:
         po = [self._output(o, f.camera_set) for o, f in zip(outputs, pf)]
         P.psweep_run(self.ctx, pf, po, _stream_handle(stream))
         if self.settings.mode == "soft":
-            # the backward re-reads the reference image of this run: hold the
-            # tensors so the caching allocator cannot hand their memory out
+            # the backward re-reads the images and the soft outputs (rho, lse)
+            # of this run through the pointers it was given: hold the tensors
+            # so the caching allocator cannot hand their memory out
             self._soft_frames = list(frames)
+            self._soft_outputs = {k: outputs[0][k] for k in ("soft_invdepth", "soft_lse")}
             self._soft_shape = tuple(outputs[0]["soft_invdepth"].shape)
+            self.soft_run_id = getattr(self, "soft_run_id", 0) + 1
 
     def capture_graph(self, frames, outputs, stream=None):
         if len(frames) != len(outputs):
@@ -259,11 +262,21 @@ class PlaneSweep:
     def plane_pixels(self, frames) -> int:
         return P.psweep_plane_pixels(self.ctx, [self._frame(f) for f in frames])
 
-    def soft_backward(self, grad_invdepth, src_shapes, stream=None, image_grads=True):
+    def plane_pixels_met(self, frames) -> int:
+        """(pixel, plane) pairs with a window inside the image whose ray meets
+        the plane (the method's own work; the rest have no cost at all)."""
+        return P.psweep_plane_pixels_met(self.ctx, [self._frame(f) for f in frames])
+
+    def soft_backward(self, grad_invdepth, src_shapes, stream=None, image_grads=True, run_id=None):
         """Gradients of sum(grad * soft_invdepth) of the last soft run: list of
         per-source image gradients (None where not requested) and a [S, 6]
         float64 pose gradient (v, omega).  image_grads: True, False, or one
-        flag per source."""
+        flag per source.  run_id: the soft_run_id the forward saw; the
+        library differentiates only the latest soft run, so an older one is
+        an error."""
+        if run_id is not None and run_id != getattr(self, "soft_run_id", None):
+            raise RuntimeError("backward of a soft run that a later run has replaced: the library "
+                               "differentiates only the latest soft run (run the forward again)")
         if tuple(grad_invdepth.shape) != getattr(self, "_soft_shape", None):
             raise ValueError("the gradient must have the shape of the last soft run's output")
         g = grad_invdepth.contiguous().float()
