@@ -193,6 +193,24 @@ psweep_status psweep_set_crop(psweep_ctx *ctx, int32_t camera_set, int32_t x, in
 psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
                          const psweep_output *out, void *hip_stream);
 
+/* psweep_run for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same maps, bitwise, with no workspace.  The run's scratch (job tables,
+ * counters, level images, textures, level maps) lives in a static device
+ * array of the library, 64 MiB per GPU, held until the process ends; each
+ * tile sweeps all its planes in one pass (no plane chunks, which would need
+ * partial-state room).  The caller passes only inputs and outputs; no
+ * psweep_set_workspace is needed.  EINVAL (with the bytes the context needs)
+ * when the context's limits (max_width x max_height, max_sources,
+ * max_frames) need more than 64 MiB, e.g. one 1024 x 768 frame with three
+ * sources needs about 35 MiB; EUNSUPPORTED in soft mode.  Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * (from any context) that overlap on one GPU race, so order them on one
+ * stream; a call after psweep_run on the same context sets its tables up
+ * again.  Calls no hipMalloc or hipFree. */
+psweep_status psweep_run_noalloc(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                                 const psweep_output *out, void *hip_stream);
+
 /* Gradient of L = sum_p g_p * soft_invdepth_p (g = d_grad_invdepth, full
  * resolution, pitch soft_pitch of the last run) with respect to every source
  * image (d_grad_src[s]: float device array of the source's size, row-major,

@@ -30,6 +30,7 @@ extern "C" size_t psw_backward_lds(int win, int n_src);
 extern "C" int psw_backward_tile_rows();
 extern "C" const void *psw_zero_kernel();
 extern "C" const void *psw_pose_reduce_kernel();
+extern "C" hipError_t psw_static_scratch(void **ptr, size_t *bytes);
 
 namespace {
 
@@ -98,6 +99,20 @@ const KernelEntry *find_kernel(int win, int rows, int waves, int n_src, int stor
 
 }  // namespace
 
+namespace {
+// Where a run's scratch lives inside its device memory (the bound workspace,
+// or the library's static scratch array): two job-table regions (direct
+// runs, graph), two counter regions, then one slot per frame with the level
+// images, textures, level maps, plane tables and plane-chunk partial states.
+struct Layout {
+    size_t table_bytes = 0, off_table[2] = {0, 0}, off_counter[2] = {0, 0}, off_slots = 0, slot_bytes = 0;
+    size_t s_ref[PSWEEP_MAX_LEVELS] = {0, 0}, s_tex[PSWEEP_MAX_LEVELS] = {0, 0}, s_maps[PSWEEP_MAX_LEVELS] = {0, 0},
+           s_htab[PSWEEP_MAX_LEVELS] = {0, 0}, s_theta[PSWEEP_MAX_LEVELS] = {0, 0}, s_part[PSWEEP_MAX_LEVELS] = {0, 0};
+    size_t need = 0;
+    bool parts = true;   // room for plane-chunk partial states
+};
+}  // namespace
+
 struct psweep_ctx {
     psweep_config cfg{};
     std::vector<CamSet> sets;
@@ -105,12 +120,14 @@ struct psweep_ctx {
     // level size bounds for the workspace
     int ref_w[PSWEEP_MAX_LEVELS] = {0, 0}, ref_h[PSWEEP_MAX_LEVELS] = {0, 0};
     int src_w[PSWEEP_MAX_LEVELS] = {0, 0}, src_h[PSWEEP_MAX_LEVELS] = {0, 0};
-    // workspace
+    // workspace (bound by the caller) and the memory the current call uses:
+    // the workspace with `full`, or the static scratch with `lean`
     char *ws = nullptr;
-    size_t ws_bytes = 0, ws_need = 0;
-    size_t table_bytes = 0, off_table[2] = {0, 0}, off_counter[2] = {0, 0}, off_slots = 0, slot_bytes = 0;
-    size_t s_ref[PSWEEP_MAX_LEVELS], s_tex[PSWEEP_MAX_LEVELS], s_maps[PSWEEP_MAX_LEVELS], s_htab[PSWEEP_MAX_LEVELS],
-        s_theta[PSWEEP_MAX_LEVELS];
+    size_t ws_bytes = 0;
+    Layout full, lean;
+    const Layout *lay = &full;
+    char *base = nullptr;
+    const char *last_base = nullptr;   // memory the device tables were uploaded to
     // pinned staging of the job tables (double buffered)
     char *staging[2] = {nullptr, nullptr};
     hipEvent_t staging_ev[2] = {nullptr, nullptr};
@@ -123,7 +140,6 @@ struct psweep_ctx {
     int tile_rows[PSWEEP_MAX_LEVELS] = {4, 4}, tile_waves[PSWEEP_MAX_LEVELS] = {4, 4};
     int chunks[PSWEEP_MAX_LEVELS] = {0, 0};   // plane chunks per tile; 0 = automatic
     int n_cu = 256;
-    size_t s_part[PSWEEP_MAX_LEVELS] = {0, 0};
     // timing of sweep launches
     bool timing = false;
     std::vector<hipEvent_t> ev0, ev1;
@@ -248,6 +264,39 @@ size_t max_items(const psweep_config &c, int l, int w, int h) {
     return tx * ty * kMaxChunks;
 }
 
+Layout make_layout(const psweep_config &cfg, const int *P, const int *ref_w, const int *ref_h, const int *src_w,
+                   const int *src_h, bool parts) {
+    Layout L;
+    L.parts = parts;
+    // table region: every kind of record for kMaxJobs jobs, and the item queues
+    size_t order_bytes = 0;
+    for (int l = 0; l < cfg.n_levels; ++l)
+        order_bytes += align_up(sizeof(int32_t) * (kQueueHead + max_items(cfg, l, ref_w[l], ref_h[l]))) *
+                       (size_t)cfg.max_frames;
+    L.table_bytes = align_up(sizeof(JobDev) * kMaxJobs) + align_up(sizeof(SetupDev) * kMaxJobs) +
+                    align_up(sizeof(PrepDev) * kMaxJobs) + align_up(sizeof(BorderDev) * kMaxJobs) +
+                    align_up(sizeof(MergeDev) * kMaxJobs) + order_bytes;
+    size_t off = 0;
+    for (int g = 0; g < 2; ++g) { L.off_table[g] = off; off += L.table_bytes; }
+    for (int g = 0; g < 2; ++g) { L.off_counter[g] = off; off += align_up(sizeof(int) * (kQueueHead + kQueues * kMaxJobs)); }
+    L.off_slots = off;
+    size_t so = 0;
+    const int S = cfg.max_sources;
+    for (int l = 0; l < cfg.n_levels; ++l) {
+        const size_t rpx = (size_t)ref_w[l] * ref_h[l];
+        const size_t spx = (size_t)src_w[l] * src_h[l];
+        L.s_ref[l] = so;   so += align_up(rpx);
+        L.s_tex[l] = so;   so += align_up(spx * texel_bytes(cfg)) * S;
+        L.s_maps[l] = so;  so += align_up(rpx * 4) * 4;
+        L.s_htab[l] = so;  so += align_up((size_t)P[l] * S * 9 * 4);
+        L.s_theta[l] = so; so += align_up((size_t)P[l] * 4);
+        L.s_part[l] = so;  so += parts ? align_up(rpx * 4 * kPartWords * kMaxChunks) : 0;
+    }
+    L.slot_bytes = align_up(so);
+    L.need = L.off_slots + L.slot_bytes * cfg.max_frames;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -277,34 +326,10 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
         ctx->ref_w[l] = ctx->src_w[l];
         ctx->ref_h[l] = ctx->src_h[l];
     }
-    // table region: every kind of record for kMaxJobs jobs
-    size_t order_bytes = 0;
-    for (int l = 0; l < cfg->n_levels; ++l)
-        order_bytes += align_up(sizeof(int32_t) * (kQueueHead + max_items(*cfg, l, ctx->ref_w[l], ctx->ref_h[l]))) *
-                       (size_t)cfg->max_frames;
-    ctx->table_bytes = align_up(sizeof(JobDev) * kMaxJobs) + align_up(sizeof(SetupDev) * kMaxJobs) +
-                       align_up(sizeof(PrepDev) * kMaxJobs) + align_up(sizeof(BorderDev) * kMaxJobs) +
-                       align_up(sizeof(MergeDev) * kMaxJobs) + order_bytes;
-    size_t off = 0;
-    for (int g = 0; g < 2; ++g) { ctx->off_table[g] = off; off += ctx->table_bytes; }
-    for (int g = 0; g < 2; ++g) { ctx->off_counter[g] = off; off += align_up(sizeof(int) * (kQueueHead + kQueues * kMaxJobs)); }
-    ctx->off_slots = off;
-    size_t so = 0;
-    const int S = cfg->max_sources;
-    for (int l = 0; l < cfg->n_levels; ++l) {
-        const size_t rpx = (size_t)ctx->ref_w[l] * ctx->ref_h[l];
-        const size_t spx = (size_t)ctx->src_w[l] * ctx->src_h[l];
-        ctx->s_ref[l] = so;   so += align_up(rpx);
-        ctx->s_tex[l] = so;   so += align_up(spx * texel_bytes(*cfg)) * S;
-        ctx->s_maps[l] = so;  so += align_up(rpx * 4) * 4;
-        ctx->s_htab[l] = so;  so += align_up((size_t)ctx->P[l] * S * 9 * 4);
-        ctx->s_theta[l] = so; so += align_up((size_t)ctx->P[l] * 4);
-        ctx->s_part[l] = so;  so += align_up(rpx * 4 * kPartWords * kMaxChunks);
-    }
-    ctx->slot_bytes = align_up(so);
-    ctx->ws_need = ctx->off_slots + ctx->slot_bytes * cfg->max_frames;
+    ctx->full = make_layout(*cfg, ctx->P, ctx->ref_w, ctx->ref_h, ctx->src_w, ctx->src_h, true);
+    ctx->lean = make_layout(*cfg, ctx->P, ctx->ref_w, ctx->ref_h, ctx->src_w, ctx->src_h, false);
     for (int b = 0; b < 2; ++b) {
-        if (hipHostMalloc((void **)&ctx->staging[b], ctx->table_bytes, hipHostMallocDefault) != hipSuccess ||
+        if (hipHostMalloc((void **)&ctx->staging[b], ctx->full.table_bytes, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&ctx->staging_ev[b], hipEventDisableTiming) != hipSuccess) {
             psweep_destroy(ctx);
             return fail(nullptr, PSWEEP_EHIP, "pinned staging allocation failed");
@@ -325,7 +350,7 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
 
 psweep_status psweep_workspace_size(const psweep_ctx *ctx, size_t *bytes) {
     if (!ctx || !bytes) return PSWEEP_EINVAL;
-    *bytes = ctx->ws_need;
+    *bytes = ctx->full.need;
     return PSWEEP_OK;
 }
 
@@ -333,7 +358,7 @@ psweep_status psweep_set_workspace(psweep_ctx *ctx, void *dev_ptr, size_t bytes)
     if (!ctx) return PSWEEP_EINVAL;
     if (!dev_ptr) return fail(ctx, PSWEEP_EINVAL, "NULL workspace");
     if (((uintptr_t)dev_ptr) % kAlign) return fail(ctx, PSWEEP_EINVAL, "workspace must be 256-byte aligned");
-    if (bytes < ctx->ws_need) return fail(ctx, PSWEEP_ENOMEM, "workspace smaller than psweep_workspace_size");
+    if (bytes < ctx->full.need) return fail(ctx, PSWEEP_ENOMEM, "workspace smaller than psweep_workspace_size");
     ctx->ws = (char *)dev_ptr;
     ctx->ws_bytes = bytes;
     ctx->last_table.clear();
@@ -555,7 +580,8 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
         for (int s = 0; s < C.n_src; ++s)
             if (!fr.src[s] || fr.src_pitch[s] < C.src[s].width)
                 return fail(ctx, PSWEEP_EINVAL, "bad source image or pitch");
-        char *slot = ctx->ws + ctx->off_slots + (size_t)f * ctx->slot_bytes;
+        const Layout &Y = *ctx->lay;
+        char *slot = ctx->base + Y.off_slots + (size_t)f * Y.slot_bytes;
         const psweep_output &O = out[f];
         int crop_x = 0, crop_y = 0, crop_w = 0, crop_h = 0;
         if (NL == 2) {
@@ -586,7 +612,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             JobDev J;
             std::memset(&J, 0, sizeof J);
             if (ds == 2) {
-                J.ref = (const uint8_t *)(slot + ctx->s_ref[l]);
+                J.ref = (const uint8_t *)(slot + Y.s_ref[l]);
                 J.ref_pitch = C.ref.width / 2;
             } else {
                 J.ref = (const uint8_t *)fr.ref + (l == 1 ? (int64_t)crop_y * fr.ref_pitch + crop_x : 0);
@@ -603,8 +629,8 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             J.step_f = L.n_fronto > 1 ? (float)((1.0 / L.near_m - 1.0 / L.far_m) / (L.n_fronto - 1)) : 0.0f;
             J.step_g = L.n_ground > 1 ? (float)((L.h_hi - L.h_lo) / (L.n_ground - 1)) : 0.0f;
             J.temperature = (float)cfg.temperature;
-            J.htab = (const float *)(slot + ctx->s_htab[l]);
-            J.theta = (const float *)(slot + ctx->s_theta[l]);
+            J.htab = (const float *)(slot + Y.s_htab[l]);
+            J.theta = (const float *)(slot + Y.s_theta[l]);
             // outputs
             if (sf) {
                 if (cfg.mode == PSWEEP_MODE_SOFT) {
@@ -626,7 +652,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
                     J.out_pitch = M.pitch ? M.pitch : rc.w;
                 } else {
                     const size_t plane = align_up((size_t)ctx->ref_w[l] * ctx->ref_h[l] * 4);
-                    char *m = slot + ctx->s_maps[l];
+                    char *m = slot + Y.s_maps[l];
                     J.index = (int32_t *)m; J.delta = (float *)(m + plane);
                     J.cost1 = (float *)(m + 2 * plane); J.cost2 = (float *)(m + 3 * plane);
                     J.out_pitch = rc.w;
@@ -643,7 +669,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             // over the launch, so that uneven tiles still balance
             {
                 const int ntile = J.tiles_x * J.tiles_y;
-                int nch = ctx->chunks[l];
+                int nch = ctx->lay->parts ? ctx->chunks[l] : 1;   // no partial-state room: one pass
                 if (nch == 0) {
                     const long long target = 28LL * ctx->n_cu * 4;
                     const long long have = (long long)ntile * waves * (cfg.launch == PSWEEP_LAUNCH_PERSISTENT ? nf : 1);
@@ -659,7 +685,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
                     while (J.nch_f + J.nch_g > kMaxChunks) { if (J.nch_f >= J.nch_g) --J.nch_f; else --J.nch_g; }
                     if (J.nch_f + J.nch_g <= 1) { J.nch_f = 0; J.nch_g = 0; }
                 }
-                J.part = (float *)(slot + ctx->s_part[l]);
+                J.part = (float *)(slot + Y.s_part[l]);
                 const int items = ntile * std::max(1, J.nch_f + J.nch_g);
                 J.first_item = first_item;
                 first_item += items;
@@ -669,7 +695,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             for (int s = 0; s < C.n_src; ++s) {
                 const LevelCam sc = level_cam(C.src[s], ds, 0, 0, 0, 0);
                 SrcDev &D = J.src[s];
-                D.tex = (const uint32_t *)(slot + ctx->s_tex[l] +
+                D.tex = (const uint32_t *)(slot + Y.s_tex[l] +
                                            align_up((size_t)ctx->src_w[l] * ctx->src_h[l] * texel_bytes(cfg)) * s);
                 D.w = sc.w; D.h = sc.h;
                 D.fx = (float)sc.fx; D.fy = (float)sc.fy; D.cx = (float)sc.cx; D.cy = (float)sc.cy; D.xi = (float)sc.xi;
@@ -686,15 +712,15 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             for (int a = 0; a < 3; ++a) Sd.gn[a] = cfg.ground_n[a];
             Sd.gd = cfg.ground_d;
             Sd.n_src = C.n_src; Sd.n_fronto = L.n_fronto; Sd.n_ground = L.n_ground;
-            Sd.htab = (float *)(slot + ctx->s_htab[l]);
-            Sd.theta = (float *)(slot + ctx->s_theta[l]);
+            Sd.htab = (float *)(slot + Y.s_htab[l]);
+            Sd.theta = (float *)(slot + Y.s_theta[l]);
             // level images
             PrepDev Pd;
             std::memset(&Pd, 0, sizeof Pd);
             Pd.ref_full = (const uint8_t *)fr.ref; Pd.ref_pitch = fr.ref_pitch;
             Pd.img = cfg.image_format;
             Pd.ref_w = C.ref.width; Pd.ref_h = C.ref.height;
-            Pd.ref_level = ds == 2 ? (uint8_t *)(slot + ctx->s_ref[l]) : nullptr;
+            Pd.ref_level = ds == 2 ? (uint8_t *)(slot + Y.s_ref[l]) : nullptr;
             Pd.downsample = ds; Pd.n_src = C.n_src;
             for (int s = 0; s < C.n_src; ++s) {
                 Pd.src_full[s] = fr.src[s]; Pd.src_pitch[s] = fr.src_pitch[s];
@@ -758,7 +784,7 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
         jobs[j].order = (const int32_t *)(tb + total);
         total += align_up(sizeof(int32_t) * orders[j]->size());
     }
-    if (total > ctx->table_bytes) return fail(ctx, PSWEEP_EINVAL, "too many frames for the table region");
+    if (total > ctx->lay->table_bytes) return fail(ctx, PSWEEP_EINVAL, "too many frames for the table region");
     blob.bytes.assign(total, 0);
     for (int j = 0; j < nj; ++j)
         std::memcpy(blob.bytes.data() + ((const char *)jobs[j].order - tb), orders[j]->data(),
@@ -800,7 +826,7 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
     {
         // the item queues' take counters of every job start at zero (a kernel,
         // not a memset: the run may be captured into a graph)
-        int *counter = (int *)(ctx->ws + ctx->off_counter[which]);
+        int *counter = (int *)(ctx->base + ctx->lay->off_counter[which]);
         int n = kQueueHead + kQueues * nj;
         void *a[] = {&counter, &n};
         PSW_HIP(hipLaunchKernel(psw_reset_kernel(), dim3(1), dim3(256), a, 0, stream), "reset");
@@ -842,7 +868,7 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
         }
         const KernelEntry *e = find_kernel(0, ctx->tile_rows[0], ctx->tile_waves[0], n_src, store, 0, 1, 0);
         if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no persistent kernel for this tile/sources/storage");
-        int *counter = (int *)(ctx->ws + ctx->off_counter[which]);
+        int *counter = (int *)(ctx->base + ctx->lay->off_counter[which]);
         int dev = 0, n_cu = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;
@@ -889,24 +915,35 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
 
 extern "C" {
 
-psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames, const psweep_output *out,
-                         void *hip_stream) {
-    if (!ctx) return PSWEEP_EINVAL;
-    if (!ctx->ws) return fail(ctx, PSWEEP_ESTATE, "psweep_set_workspace has not been called");
+}  // extern "C"
+
+namespace {
+
+// One run on device memory `base` laid out as `lay` (the bound workspace, or
+// the static scratch of psweep_run_noalloc).
+psweep_status run_on(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames, const psweep_output *out,
+                     void *hip_stream, char *base, const Layout *lay) {
     if (!frames || !out) return fail(ctx, PSWEEP_EINVAL, "NULL frames or outputs");
     if (n_frames < 1 || n_frames > ctx->cfg.max_frames) return fail(ctx, PSWEEP_EINVAL, "n_frames out of range");
     if (ctx->cfg.mode == PSWEEP_MODE_SOFT && n_frames != 1) return fail(ctx, PSWEEP_EINVAL, "soft mode runs one frame");
     hipStream_t stream = (hipStream_t)hip_stream;
+    ctx->base = base;
+    ctx->lay = lay;
+    if (base != ctx->last_base) {
+        // the device tables and plane setup of the other memory do not apply here
+        ctx->last_table.clear();
+        ctx->setup_version = 0;
+        ctx->last_base = base;
+    }
     Blob blob;
     std::vector<int> job_frame;
-    char *tb = ctx->ws + ctx->off_table[0];
-    psweep_status st =
-        build_tables(ctx, frames, n_frames, out, tb, (int *)(ctx->ws + ctx->off_counter[0]), blob, job_frame);
+    char *tb = base + lay->off_table[0];
+    psweep_status st = build_tables(ctx, frames, n_frames, out, tb, (int *)(base + lay->off_counter[0]), blob, job_frame);
     if (st != PSWEEP_OK) return st;
     std::vector<JobDev> hj(blob.nj);
     std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);
     // upload the tables when they changed (the device copy stays valid: only
-    // psweep_run writes this region)
+    // runs on this memory write this region)
     const bool changed = blob.bytes != ctx->last_table;
     if (changed) {
         const int b = ctx->staging_idx;
@@ -933,12 +970,40 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
         ctx->soft_rho = out[0].soft_invdepth;
         ctx->soft_lse = out[0].soft_lse;
         ctx->soft_pitch = out[0].soft_pitch ? out[0].soft_pitch : hj[0].w;
-        ctx->soft_job_off = ctx->off_table[0] + blob.jobs;
+        ctx->soft_job_off = lay->off_table[0] + blob.jobs;
         ctx->soft_part = reinterpret_cast<char *>(hj[0].part);
     } else {
         ctx->soft_ready = false;
     }
     return PSWEEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames, const psweep_output *out,
+                         void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (!ctx->ws) return fail(ctx, PSWEEP_ESTATE, "psweep_set_workspace has not been called");
+    return run_on(ctx, frames, n_frames, out, hip_stream, ctx->ws, &ctx->full);
+}
+
+psweep_status psweep_run_noalloc(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_frames,
+                                 const psweep_output *out, void *hip_stream) {
+    if (!ctx) return PSWEEP_EINVAL;
+    if (ctx->cfg.mode == PSWEEP_MODE_SOFT)
+        return fail(ctx, PSWEEP_EUNSUPPORTED, "psweep_run_noalloc sweeps in winner-take-all mode only");
+    void *scratch = nullptr;
+    size_t bytes = 0;
+    const hipError_t e = psw_static_scratch(&scratch, &bytes);
+    if (e != hipSuccess) return hip_fail(ctx, e, "static scratch address");
+    if (ctx->lean.need > bytes)
+        return fail(ctx, PSWEEP_EINVAL,
+                    "psweep_run_noalloc: this context needs " + std::to_string(ctx->lean.need) +
+                        " bytes of scratch, more than the library's static " + std::to_string(bytes) +
+                        " (smaller max_width / max_height / max_sources / max_frames)");
+    return run_on(ctx, frames, n_frames, out, hip_stream, (char *)scratch, &ctx->lean);
 }
 
 psweep_status psweep_sweep_kernel_ms(psweep_ctx *ctx, double *ms, int32_t *n_launches) {
@@ -985,9 +1050,11 @@ psweep_status psweep_graph_capture(psweep_ctx *ctx, const psweep_frame *frames, 
     PSW_HIP(hipDeviceSynchronize(), "synchronise before capture");
     Blob blob;
     std::vector<int> job_frame;
-    char *tb = ctx->ws + ctx->off_table[1];
+    ctx->base = ctx->ws;
+    ctx->lay = &ctx->full;
+    char *tb = ctx->ws + ctx->full.off_table[1];
     psweep_status st =
-        build_tables(ctx, frames, n_frames, out, tb, (int *)(ctx->ws + ctx->off_counter[1]), blob, job_frame);
+        build_tables(ctx, frames, n_frames, out, tb, (int *)(ctx->ws + ctx->full.off_counter[1]), blob, job_frame);
     if (st != PSWEEP_OK) return st;
     std::vector<JobDev> hj(blob.nj);
     std::memcpy(hj.data(), blob.bytes.data() + blob.jobs, sizeof(JobDev) * blob.nj);

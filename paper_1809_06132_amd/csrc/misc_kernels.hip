@@ -1,7 +1,10 @@
 // Small kernels around the sweep: FP64 per-plane setup, level images,
-// border marks, the work counter reset and the level merge.
+// border marks, the work counter reset and the level merge; and the static
+// scratch array of psweep_run_noalloc.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <mutex>
 
 #include "sweep_common.h"
 
@@ -364,6 +367,34 @@ __global__ void mask_kernel(MaskDev M) {
 }
 
 }  // namespace psw
+
+// Scratch of psweep_run_noalloc: job tables, counters, level images,
+// textures and level maps of one run, for callers that cannot allocate.
+// Every GPU the library runs on holds one copy until the process ends; host
+// code uses its device address (from hipGetSymbolAddress, taken once per
+// device with that device current), never the array's name.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+extern "C" hipError_t psw_static_scratch(void **ptr, size_t *bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kStaticScratchBytes;
+    return hipSuccess;
+}
 
 extern "C" {
 const void *psw_filter_kernel() { return (const void *)&psw::filter_kernel; }

@@ -24,7 +24,7 @@ _d, _i32, _i64, _p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_v
 
 # every symbol include/psweep.h declares
 EXPORTS = ["psweep_create", "psweep_workspace_size", "psweep_set_workspace", "psweep_set_cameras",
-           "psweep_set_crop", "psweep_run", "psweep_soft_depth_backward", "psweep_set_tile",
+           "psweep_set_crop", "psweep_run", "psweep_run_noalloc", "psweep_soft_depth_backward", "psweep_set_tile",
            "psweep_graph_capture", "psweep_graph_launch", "psweep_set_timing", "psweep_sweep_kernel_ms",
            "psweep_sweep_kernel_times", "psweep_set_chunks", "psweep_filter", "psweep_mask_boxes",
            "psweep_plane_pixels", "psweep_plane_pixels_met", "psweep_destroy", "psweep_last_error", "psweep_version",
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
     L.psweep_set_cameras.argtypes = [_p, _i32, P(psweep_camera), _i32, P(psweep_camera), P(psweep_pose)]
     L.psweep_set_crop.argtypes = [_p, _i32, _i32, _i32, _i32, _i32]
     L.psweep_run.argtypes = [_p, P(psweep_frame), _i32, P(psweep_output), _p]
+    L.psweep_run_noalloc.argtypes = [_p, P(psweep_frame), _i32, P(psweep_output), _p]
     L.psweep_soft_depth_backward.argtypes = [_p, _p, P(_p), _p, _p]
     L.psweep_set_tile.argtypes = [_p, _i32, _i32, _i32]
     L.psweep_set_chunks.argtypes = [_p, _i32, _i32]
@@ -181,6 +182,13 @@ def psweep_run(ctx, frames, outputs, stream: int = 0):
     fa = (psweep_frame * n)(*frames)
     oa = (psweep_output * n)(*outputs)
     _check(lib().psweep_run(ctx, fa, n, oa, stream), ctx)
+
+
+def psweep_run_noalloc(ctx, frames, outputs, stream: int = 0):
+    n = len(frames)
+    fa = (psweep_frame * n)(*frames)
+    oa = (psweep_output * n)(*outputs)
+    _check(lib().psweep_run_noalloc(ctx, fa, n, oa, stream), ctx)
 
 
 def psweep_soft_depth_backward(ctx, grad_invdepth: int, grad_src_ptrs, grad_pose: int, stream: int = 0):

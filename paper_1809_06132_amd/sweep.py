@@ -226,6 +226,15 @@ class PlaneSweep:
             self._soft_shape = tuple(outputs[0]["soft_invdepth"].shape)
             self.soft_run_id = getattr(self, "soft_run_id", 0) + 1
 
+    def run_noalloc(self, frames, outputs, stream=None):
+        """The same run through psweep_run_noalloc: the library's static
+        scratch instead of the workspace (winner-take-all mode)."""
+        if len(frames) != len(outputs):
+            raise ValueError("one output per frame")
+        pf = [self._frame(f) for f in frames]
+        po = [self._output(o, f.camera_set) for o, f in zip(outputs, pf)]
+        P.psweep_run_noalloc(self.ctx, pf, po, _stream_handle(stream))
+
     def capture_graph(self, frames, outputs, stream=None):
         if len(frames) != len(outputs):
             raise ValueError("one output per frame")
