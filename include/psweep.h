@@ -203,7 +203,7 @@ psweep_status psweep_run(psweep_ctx *ctx, const psweep_frame *frames, int32_t n_
  * psweep_set_workspace is needed.  EINVAL (with the bytes the context needs)
  * when the context's limits (max_width x max_height, max_sources,
  * max_frames) need more than 64 MiB, e.g. one 1024 x 768 frame with three
- * sources needs about 35 MiB; EUNSUPPORTED in soft mode.  Every call on one
+ * sources needs about 31 MiB; EUNSUPPORTED in soft mode.  Every call on one
  * GPU shares that GPU's array, which keeps the last call's contents: calls
  * (from any context) that overlap on one GPU race, so order them on one
  * stream; a call after psweep_run on the same context sets its tables up
