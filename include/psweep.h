@@ -153,6 +153,16 @@ typedef struct {
     float *soft_invdepth;                     /* soft mode, full resolution */
     float *soft_lse;                          /* soft mode: log-sum-exp of -cost / T */
     int64_t soft_pitch;
+    /* Optional (NULL = not written), winner-take-all mode with the grid
+     * launch: per level, the aggregated cost of every (pixel, plane) of the
+     * level (mean of the best_k source costs; +inf where no source window is
+     * usable), device floats [P][h][w] at the level's size, plane k at
+     * offset k * w * h.  Written only for pixels whose window lies inside the
+     * level image, and not for a (pixel, plane family) the sweep skips (a
+     * wave of pixels without a textured reference window or a ray that meets
+     * the family): fill it with +inf beforehand.  For parity tests of every
+     * cost; it costs one store per (pixel, plane). */
+    float *cost_volume[PSWEEP_MAX_LEVELS];
 } psweep_output;
 
 /* Create a context for `cfg`.  EINVAL on inconsistent settings (even window,

@@ -80,7 +80,7 @@ def lib():
     L.or_plane_param.restype = _d
     L.or_warp.argtypes = [PR, PC, PC, PP, ctypes.c_int, _d, _d, _p, _p, _p]
     L.or_warp.restype = ctypes.c_int
-    L.or_sweep.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i64, _p] + [_p] * 10
+    L.or_sweep.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i64, _p] + [_p] * 11
     L.or_sweep.restype = None
     L.or_window_cost.argtypes = [PR, PC, PI, PC, PI, PP, _i32, _i32, _i32, _p]
     L.or_window_cost.restype = None
@@ -211,14 +211,16 @@ def window_cost(level, settings, ref_cam, ref_img, src_cam, src_img, ps, k, i, j
 # one level
 # ----------------------------------------------------------------------------
 def sweep_level(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, pixels=None,
-                volume: bool = False, srcvol: bool = False):
+                volume: bool = False, srcvol: bool = False, srcsig: bool = False):
     """Winner-take-all plane sweep of one level (Sec. III-A).
 
     pixels: None (every pixel) or an int array [n, 2] of (x, y).
     Returns a dict of per-pixel arrays (shape [H, W] for all pixels, [n]
     otherwise): depth (range), z, index, delta, cost1, cost2, cost2_nonadj,
-    param (refined plane parameter), optionally volume [.., P] and
-    srcvol [.., P, S]."""
+    param (refined plane parameter), optionally volume [.., P],
+    srcvol [.., P, S] and srcsig [.., P, S] (standard deviation of each
+    source window's samples; NaN where a sample is unusable, set also for
+    windows below the variance floor)."""
     H, W = ref_img.shape
     if pixels is None:
         n, pix, shape = H * W, None, (H, W)
@@ -231,6 +233,7 @@ def sweep_level(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, pi
     out["index"] = np.empty(n, np.int32)
     vol = np.empty((n, P), np.float64) if volume else None
     svol = np.empty((n, P, S), np.float64) if srcvol else None
+    ssig = np.empty((n, P, S), np.float64) if srcsig else None
     R = _Img(ref_img)
     Ss = [_Img(s) for s in src_imgs]
     sarr = (OrImage * S)(*[s.s for s in Ss])
@@ -240,12 +243,14 @@ def sweep_level(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, pi
                    carr, sarr, parr, n, _ptr(pix),
                    out["depth"].ctypes.data, out["z"].ctypes.data, out["index"].ctypes.data,
                    out["delta"].ctypes.data, out["cost1"].ctypes.data, out["cost2"].ctypes.data,
-                   out["cost2_nonadj"].ctypes.data, out["param"].ctypes.data, _ptr(vol), _ptr(svol))
+                   out["cost2_nonadj"].ctypes.data, out["param"].ctypes.data, _ptr(vol), _ptr(svol), _ptr(ssig))
     res = {k: v.reshape(shape) for k, v in out.items()}
     if volume:
         res["volume"] = vol.reshape(shape + (P,))
     if srcvol:
         res["srcvol"] = svol.reshape(shape + (P, S))
+    if srcsig:
+        res["srcsig"] = ssig.reshape(shape + (P, S))
     return res
 
 

@@ -170,6 +170,7 @@ static int bilinear(const or_image *im, double u, double v, double *val,
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int valid;
+    int sampled;   /* every window sample usable: the window statistics are set */
     double zncc, cost;
     double mean_a, mean_b, s_aa, s_bb, s_ab;
 } win_stats;
@@ -216,6 +217,7 @@ static win_stats pixel_cost(const or_params *p, const or_camera *rc, const or_im
             saa += a * a; sbb += b * b; sab += a * b;
         }
     st.mean_a = ma; st.mean_b = mb; st.s_aa = saa; st.s_bb = sbb; st.s_ab = sab;
+    st.sampled = 1;
     if (saa <= N * p->var_floor || sbb <= N * p->var_floor) return st;
     double z = sab / sqrt(saa * sbb);
     if (z > 1.0) z = 1.0;
@@ -252,10 +254,12 @@ static double aggregate(int S, int K, const double *c, const int *valid, int *ch
 }
 
 /* Aggregated cost of pixel (i, j) for every plane (NaN = invalid) and,
- * optionally, every per-source cost (NaN = invalid). */
+ * optionally, every per-source cost (NaN = invalid) and the standard
+ * deviation of every source window's samples, sqrt(s_bb / N) (NaN where a
+ * sample is unusable; set also below the variance floor). */
 static void pixel_costs(const or_params *p, const or_camera *rc, const or_image *ref, int S,
                         const or_camera *scs, const or_image *srcs, const or_pose *poses,
-                        int i, int j, double *C, double *Cs)
+                        int i, int j, double *C, double *Cs, double *Sig)
 {
     const int P = n_planes(p);
     double cs[64];
@@ -267,6 +271,7 @@ static void pixel_costs(const or_params *p, const or_camera *rc, const or_image 
             vs[s] = st.valid;
             cs[s] = st.cost;
             if (Cs) Cs[(int64_t)k * S + s] = st.valid ? st.cost : NAN;
+            if (Sig) Sig[(int64_t)k * S + s] = st.sampled ? sqrt(st.s_bb / (p->window * p->window)) : NAN;
         }
         C[k] = aggregate(S, p->best_k, cs, vs, NULL);
     }
@@ -304,12 +309,15 @@ double or_parabola(double cm, double c0, double cp)
  *   param  refined plane parameter (rho or h), NaN if invalid
  *   volume aggregated cost per plane [n_pix][P] (NaN = invalid)
  *   srcvol per-source cost [n_pix][P][S] (NaN = invalid)
+ *   srcsig per-source standard deviation of the window's samples [n_pix][P][S]
+ *          (NaN where a sample is unusable; set also for windows below the
+ *          variance floor)
  */
 void or_sweep(const or_params *p, const or_camera *rc, const or_image *ref, int32_t S,
               const or_camera *scs, const or_image *srcs, const or_pose *poses,
               int64_t n_pix, const int32_t *pix,
               double *depth, double *z, int32_t *index, double *delta, double *c1, double *c2,
-              double *c2na, double *param, double *volume, double *srcvol)
+              double *c2na, double *param, double *volume, double *srcvol, double *srcsig)
 {
     const int P = n_planes(p);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -317,7 +325,8 @@ void or_sweep(const or_params *p, const or_camera *rc, const or_image *ref, int3
         int i = pix ? pix[2 * e] : (int)(e % ref->width);
         int j = pix ? pix[2 * e + 1] : (int)(e / ref->width);
         double *C = (double *)malloc(sizeof(double) * P);
-        pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, srcvol ? srcvol + e * P * S : NULL);
+        pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, srcvol ? srcvol + e * P * S : NULL,
+                    srcsig ? srcsig + e * P * S : NULL);
         if (volume) memcpy(volume + e * P, C, sizeof(double) * P);
         int kb = -1;
         double b1 = INFINITY, b2 = INFINITY, bna = INFINITY;
@@ -498,7 +507,7 @@ void or_soft_forward(const or_params *p, const or_camera *rc, const or_image *re
         int i = pix ? pix[2 * e] : (int)(e % ref->width);
         int j = pix ? pix[2 * e + 1] : (int)(e / ref->width);
         double *C = (double *)malloc(sizeof(double) * P);
-        pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, NULL);
+        pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, NULL, NULL);
         double m = -INFINITY;
         for (int k = 0; k < P; ++k)
             if (!isnan(C[k]) && -C[k] / p->temperature > m) m = -C[k] / p->temperature;
@@ -546,7 +555,7 @@ void or_soft_backward(const or_params *p, const or_camera *rc, const or_image *r
             const int i = x0 + ii, j = y0 + jj;
             const double gp = g[(int64_t)jj * w + ii];
             if (gp == 0.0) continue;
-            pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, Cs);
+            pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, Cs, NULL);
             double m = -INFINITY;
             for (int k = 0; k < P; ++k)
                 if (!isnan(C[k]) && -C[k] / T > m) m = -C[k] / T;

@@ -629,6 +629,11 @@ psweep_status build_tables(psweep_ctx *ctx, const psweep_frame *frames, int nf, 
             J.step_f = L.n_fronto > 1 ? (float)((1.0 / L.near_m - 1.0 / L.far_m) / (L.n_fronto - 1)) : 0.0f;
             J.step_g = L.n_ground > 1 ? (float)((L.h_hi - L.h_lo) / (L.n_ground - 1)) : 0.0f;
             J.temperature = (float)cfg.temperature;
+            if (O.cost_volume[l]) {
+                if (cfg.mode != PSWEEP_MODE_WTA || cfg.launch != PSWEEP_LAUNCH_GRID)
+                    return fail(ctx, PSWEEP_EUNSUPPORTED, "cost volumes come from winner-take-all grid launches");
+                J.volume = O.cost_volume[l];
+            }
             J.htab = (const float *)(slot + Y.s_htab[l]);
             J.theta = (const float *)(slot + Y.s_theta[l]);
             // outputs

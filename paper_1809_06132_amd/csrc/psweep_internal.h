@@ -60,6 +60,7 @@ struct JobDev {
     // queue_ctr: the eight queues' take counters (zeroed before the launch).
     const int32_t *order;
     int32_t *queue_ctr;
+    float *volume;         // optional [P][h][w] aggregated costs (psweep_output::cost_volume)
     SrcDev src[kMaxSrc];
 };
 

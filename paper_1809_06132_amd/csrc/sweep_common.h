@@ -366,7 +366,7 @@ __device__ __forceinline__ void finish_soft(const JobDev &J, int orow, int col, 
 // ---------------------------------------------------------------------------
 // the sweep of one tile
 // ---------------------------------------------------------------------------
-template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0, bool K2 = false>
+template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0, bool K2 = false, bool VOL = false>
 struct Tile {
     static constexpr int HW = WIN / 2;
     static constexpr int TXO = kWave - 2 * HW;       // output columns per tile
@@ -675,6 +675,8 @@ struct Tile {
                         float C = K2 ? aggregate2<S>(cs4) : aggregate<S>(cs4, K);
                         if (!kScalarMasks) C = ((ref_ok >> i) & 1u) ? C : PSW_INF;
                         if (kk == 0) cfirst[i] = C;
+                        if (VOL && ((pos_ok >> i) & 1u))
+                            gptr(J.volume)[((int64_t)k * H + or0 + i) * W + sc] = C;
                         if (!SOFT) {
                             // branch-free: with c1 <= c2 (no NaN reaches here) the new
                             // second best is med3(c1, c2, C) and the new best min(c1, C);
@@ -769,11 +771,19 @@ __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__r
     const int tile = item - chunk * ntile;
     const int tile_y = tile / tx;
     const int r = tile - tile_y * tx;
-    // the mean of the best two sources (the usual setting) has a short form
-    if (!SOFT && S >= 2 && job->best_k == 2)
-        Tile<WIN, R, NW, S, STORE, SOFT, IMG, true>::run(job, r % tx, tile_y, chunk, smem, threadIdx.x & (kWave - 1));
-    else
-        Tile<WIN, R, NW, S, STORE, SOFT, IMG>::run(job, r % tx, tile_y, chunk, smem, threadIdx.x & (kWave - 1));
+    // the mean of the best two sources (the usual setting) has a short form;
+    // the cost volume output has kernels of its own
+    const int lane = threadIdx.x & (kWave - 1);
+    if (!SOFT && job->volume) {
+        if (S >= 2 && job->best_k == 2)
+            Tile<WIN, R, NW, S, STORE, SOFT, IMG, true, true>::run(job, r % tx, tile_y, chunk, smem, lane);
+        else
+            Tile<WIN, R, NW, S, STORE, SOFT, IMG, false, true>::run(job, r % tx, tile_y, chunk, smem, lane);
+    } else if (!SOFT && S >= 2 && job->best_k == 2) {
+        Tile<WIN, R, NW, S, STORE, SOFT, IMG, true>::run(job, r % tx, tile_y, chunk, smem, lane);
+    } else {
+        Tile<WIN, R, NW, S, STORE, SOFT, IMG>::run(job, r % tx, tile_y, chunk, smem, lane);
+    }
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }

@@ -82,7 +82,7 @@ class psweep_tsdf_config(ctypes.Structure):
 
 class psweep_output(ctypes.Structure):
     _fields_ = [("merged", psweep_maps), ("level", psweep_maps * MAX_LEVELS), ("soft_invdepth", _p),
-                ("soft_lse", _p), ("soft_pitch", _i64)]
+                ("soft_lse", _p), ("soft_pitch", _i64), ("cost_volume", _p * MAX_LEVELS)]
 
 
 @functools.lru_cache(maxsize=1)

@@ -147,6 +147,13 @@ class PlaneSweep:
                              for l in range(len(self.settings.levels))]
         return out
 
+    def alloc_cost_volumes(self, camera_set=0):
+        """Per level, a [P, h, w] float32 tensor filled with +inf, to pass as
+        outputs["cost_volume"] (the sweep writes every (pixel, plane) cost it
+        computes; the pairs it skips keep +inf)."""
+        return [torch.full((lv.n_fronto + lv.n_ground,) + tuple(self.level_size(camera_set, l)), math.inf,
+                           dtype=torch.float32, device=self.device) for l, lv in enumerate(self.settings.levels)]
+
     # -- marshalling --------------------------------------------------------
     @staticmethod
     def _maps(m: dict | None, shape=None) -> P.psweep_maps:
@@ -198,6 +205,14 @@ class PlaneSweep:
         po.merged = self._maps(o.get("merged"), full)
         for l, m in enumerate(o.get("levels", []) or []):
             po.level[l] = self._maps(m, self.level_size(camera_set, l))
+        for l, vol in enumerate(o.get("cost_volume", []) or []):
+            if vol is None:
+                continue
+            lv = self.settings.levels[l]
+            want = (lv.n_fronto + lv.n_ground,) + tuple(self.level_size(camera_set, l))
+            if not (vol.is_cuda and vol.is_contiguous() and vol.dtype == torch.float32 and tuple(vol.shape) == want):
+                raise ValueError(f"cost volume of level {l} must be a contiguous float32 CUDA tensor of shape {want}")
+            po.cost_volume[l] = vol.data_ptr()
         if "soft_invdepth" in o:
             for key in ("soft_invdepth", "soft_lse"):
                 t = o[key]
