@@ -146,74 +146,85 @@ def cpu_baseline(fr, st, target_s=15.0, one_core_s=5.0):
             "valid_source_evaluation_share": valid_share}
 
 
-def bench_c5(args):
+class _C5:
     """C5: 16 frame sets of mixed size (1280x960 / 1024x768 / 640x480), 4
-    sources, two levels of 192 + 64 planes.  The batched form (one
-    persistent launch for every frame, level and tile, FP16 staging, replayed
-    as a HIP graph) against plain per-frame FP32 launches."""
-    import torch
+    sources, two levels of 192 + 64 planes, resident on the GPU."""
 
-    import scenegen
-    from paper_1809_06132_amd.sweep import PlaneSweep, frame_to_device
+    def __init__(self):
+        import scenegen
+        from paper_1809_06132_amd.sweep import frame_to_device
+        wl = scenegen.workload("C5")
+        self.frames = wl.frames
+        self.W, self.H = scenegen.C5_SIZES[0]
+        self.st = scenegen.c5_settings(self.W, self.H)
+        self.dev = []
+        for i, fr in enumerate(self.frames):
+            d = frame_to_device(fr)
+            d["camera_set"] = i
+            self.dev.append(d)
 
-    wl = scenegen.workload("C5")
-    frames = wl.frames
-    W, H = scenegen.C5_SIZES[0]
-    st = scenegen.c5_settings(W, H)
-    dev = []
-    for i, fr in enumerate(frames):
-        d = frame_to_device(fr)
-        d["camera_set"] = i
-        dev.append(d)
-
-    def setup(ps):
-        for i, fr in enumerate(frames):
+    def sweep(self, storage, launch, max_frames):
+        from paper_1809_06132_amd.sweep import PlaneSweep
+        ps = PlaneSweep(self.st, self.W, self.H, 4, max_frames=max_frames, max_camera_sets=len(self.frames),
+                        storage=storage, launch=launch)
+        for i, fr in enumerate(self.frames):
             ps.set_cameras(i, fr.ref_cam, fr.src_cams, fr.poses)
             w, h = fr.ref_cam.width, fr.ref_cam.height
             ps.set_crop(i, (w - w // 2) // 2, (h - h // 2) // 2, w // 2, h // 2)
+        outs = [ps.alloc_outputs(camera_set=i) for i in range(len(self.frames))]
+        return ps, outs
 
-    from paper_1809_06132_amd import autotune
+    def plain_ms(self, steps, warmup):
+        """Plain form: one frame per run, FP32 staging, per-level grid launches."""
+        import torch
+        ps, outs = self.sweep("f32", "grid", 1)
+        pp = sum(ps.plane_pixels([d]) for d in self.dev)
+        for _ in range(warmup):
+            for d, o in zip(self.dev, outs):
+                ps.run([d], [o])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for d, o in zip(self.dev, outs):
+                ps.run([d], [o])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        ps.close()
+        return ms, pp
 
-    res, tuned = {}, {}
-    # plain: one frame per run, FP32 staging, per-level grid launches
-    ps = PlaneSweep(st, W, H, 4, max_frames=1, max_camera_sets=len(frames), storage="f32", launch="grid")
-    setup(ps)
-    outs = [ps.alloc_outputs(camera_set=i) for i in range(len(frames))]
-    pp = sum(ps.plane_pixels([d]) for d in dev)
-    for _ in range(args.warmup):
-        for d, o in zip(dev, outs):
-            ps.run([d], [o])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for d, o in zip(dev, outs):
-            ps.run([d], [o])
-    torch.cuda.synchronize()
-    res["plain_f32_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
-    ps.close()
-    # batched: all frames in one run captured as a HIP graph, either one
-    # persistent launch over every (frame, level, tile, chunk) or one grid
-    # per (frame, level)
-    for storage, launch in (("f16", "persistent"), ("f32", "persistent"), ("f16", "grid"), ("f32", "grid")):
-        ps = PlaneSweep(st, W, H, 4, max_frames=len(frames), max_camera_sets=len(frames), storage=storage,
-                        launch=launch)
-        setup(ps)
-        outs = [ps.alloc_outputs(camera_set=i) for i in range(len(frames))]
-        # tile shape, then plane chunks per level, picked by the autotuner on
-        # this very batch (no cache: tuned afresh every time)
-        choice = autotune.tune(ps, dev, outs, reps=3, cache_path=None)
-        tuned[f"{launch}_{storage}"] = {"tiles": choice["tiles"], "chunks": choice["chunks"]}
-        ps.capture_graph(dev, outs)
-        for _ in range(args.warmup):
+    def batched_ms(self, storage, launch, steps, warmup):
+        """Batched form: every frame in one run captured as a HIP graph, the
+        tile shape and plane chunks per level picked by the autotuner on this
+        very batch (tuned afresh, no cache)."""
+        import torch
+        from paper_1809_06132_amd import autotune
+        ps, outs = self.sweep(storage, launch, len(self.frames))
+        choice = autotune.tune(ps, self.dev, outs, reps=3, cache_path=None)
+        ps.capture_graph(self.dev, outs)
+        for _ in range(warmup):
             ps.launch_graph()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             ps.launch_graph()
         torch.cuda.synchronize()
-        res[f"batched_{launch}_{storage}_graph_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
+        ms = (time.perf_counter() - t0) / steps * 1e3
         ps.close()
-    line = {"metric": METRIC, "workload": "C5", "plane_pixels_per_batch": pp, "maps_per_batch": len(frames)}
+        return ms, {"tiles": choice["tiles"], "chunks": choice["chunks"]}
+
+
+def bench_c5(args):
+    """C5: the batched form (one persistent launch for every frame, level and
+    tile, or one grid per frame and level; FP16 or FP32 staging; replayed as
+    a HIP graph) against plain per-frame FP32 launches."""
+    c5 = _C5()
+    res, tuned = {}, {}
+    res["plain_f32_ms"], pp = c5.plain_ms(args.steps, args.warmup)
+    for storage, launch in (("f16", "persistent"), ("f32", "persistent"), ("f16", "grid"), ("f32", "grid")):
+        ms, choice = c5.batched_ms(storage, launch, args.steps, args.warmup)
+        res[f"batched_{launch}_{storage}_graph_ms"] = ms
+        tuned[f"{launch}_{storage}"] = choice
+    line = {"metric": METRIC, "workload": "C5", "plane_pixels_per_batch": pp, "maps_per_batch": len(c5.frames)}
     for k, v in res.items():
         line[k] = v
         line[k.replace("_ms", "_gpps")] = pp / (v * 1e-3) / 1e9
@@ -221,7 +232,33 @@ def bench_c5(args):
     line["autotuned"] = tuned
     line["best_batched"] = best
     line["best_batched_vs_plain_f32"] = res["plain_f32_ms"] / res[best]
+    if not args.no_cpu:
+        line["cpu_baseline"] = _c5_cpu_baseline(c5)
     print(json.dumps(line), flush=True)
+
+
+def _c5_cpu_baseline(c5, seconds=10.0):
+    """The FP64 oracle on random pixels of the batch's first frame (1280x960),
+    both levels with all their planes: plane-pixel evaluations per second."""
+    import numpy as np
+
+    import oracle
+    import scenegen
+    fr = c5.frames[0]
+    st = scenegen.c5_settings(fr.ref_cam.width, fr.ref_cam.height)
+    rng = np.random.default_rng(7)
+    done, t0, n = 0, time.perf_counter(), 256
+    while time.perf_counter() - t0 < seconds:
+        for lv in st.levels:
+            rc, rimg, scs, simgs = oracle.level_inputs(fr, lv)
+            h, w = rimg.shape
+            px = np.stack([rng.integers(0, w, n), rng.integers(0, h, n)], 1).astype(np.int32)
+            oracle.sweep_level(lv, st, rc, rimg, scs, simgs, fr.poses, pixels=px)
+            done += n * (lv.n_fronto + lv.n_ground)
+    dt = time.perf_counter() - t0
+    return {"value": done / dt / 1e9, "unit": "Gpix·planes/s", "cores": oracle.threads(), "cpu": cpu_model(),
+            "kind": "oracle", "sample": f"random pixels of both levels of the 1280x960 frame, all 256 planes x 4 "
+                                        f"sources, FP64, {dt:.1f} s"}
 
 
 def _time_runs(ps, frames, outs, steps, warmup):
@@ -275,17 +312,51 @@ def bench_levels(args):
         out = ps.alloc_outputs()
         pp = ps.plane_pixels([d])
         med, pct = _time_runs(ps, [d], [out], args.steps, args.warmup)
+        torch.cuda.synchronize()
+        maps = {k: v.cpu().numpy() for k, v in out["merged"].items()}
         ps.close()
         rows.append({"workload": name, "cameras": len(srcs) + 1, "storage": storage, "launch": launch,
                      "ms_per_map": med,
                      "ms_p10_p50_p90": pct, "maps_per_s": 1e3 / med, "plane_pixels_per_map": pp,
                      "gpix_planes_per_s": pp / (med * 1e-3) / 1e9})
+        if name == "C3" and not args.no_cpu:
+            rows[-1]["vs_oracle"] = _accuracy(maps, _c3_oracle(fr, st))
     line = {"metric": METRIC, "workload": args.workload, "results": rows}
+    if args.workload == "C3" and not args.no_cpu:
+        ref, secs = _c3_oracle.cache
+        import oracle
+        line["cpu_baseline"] = {"value": 1.0 / secs, "unit": "maps/s", "cores": oracle.threads(), "cpu": cpu_model(),
+                                "kind": "oracle", "sample": "the whole two-level 1024x768 map (both levels at every "
+                                "pixel, then the merge), FP64, one run"}
     if args.workload == "paper":
         line["context"] = ("the paper's multi-scale depth stage: 36 ms per frame with 5 cameras on a GTX 1080; "
                            "3 cameras about 17% less")
         line["three_vs_five_cameras_time_ratio"] = rows[1]["ms_per_map"] / rows[0]["ms_per_map"]
     print(json.dumps(line), flush=True)
+
+
+def _c3_oracle(fr, st):
+    """The FP64 oracle's two-level map of the frame (computed once, timed)."""
+    if getattr(_c3_oracle, "cache", None) is None:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.run(fr, st)["merged"]
+        _c3_oracle.cache = (ref, time.perf_counter() - t0)
+    return _c3_oracle.cache[0]
+
+
+def _accuracy(gpu, ref):
+    """Merged map against the oracle's: level and index agreement over the
+    oracle's valid pixels, and the range's relative error on the pixels
+    whose level and index agree (p50, p99.9, max)."""
+    import numpy as np
+    ov = ref["level"] != 255
+    same = ov & (gpu["level"] == ref["level"]) & (gpu["index"] == ref["index"])
+    rel = np.abs(gpu["depth"][same] - ref["depth"][same]) / ref["depth"][same]
+    return {"pixels": int(ov.sum()), "level_agreement": float((gpu["level"][ov] == ref["level"][ov]).mean()),
+            "index_agreement": float(same.sum() / ov.sum()),
+            "depth_rel_err_p50_p999_max": [float(np.quantile(rel, 0.5)), float(np.quantile(rel, 0.999)),
+                                           float(rel.max())]}
 
 
 def bench_c4(args):
@@ -487,6 +558,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="default workload: skip the batched-vs-plain comparison on the 16-frame batch")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5", "paper", "tsdf", "filter"],
                     help="C2 (default): the benchmark line; C3: two-level maps per staging precision; "
@@ -607,6 +680,20 @@ def main():
                              "counted_frac": None if traffic is None else traffic / (kernel_ms * 1e-3) / HBM_PEAK}},
     }
     ps.close()
+    if not args.no_batched:
+        # the batched form against the plain FP32 form (the metric's second
+        # half): 16 mixed-size frames, FP16 staging, one persistent launch in a
+        # HIP graph, tiles and chunks autotuned on the batch
+        c5 = _C5()
+        plain, pp5 = c5.plain_ms(max(3, args.steps // 10), 2)
+        batched, choice = c5.batched_ms("f16", "persistent", max(3, args.steps // 10), 2)
+        line["batched_vs_plain_f32"] = {
+            "workload": "C5: 16 frame sets (6 x 1280x960, 5 x 1024x768, 5 x 640x480), 4 sources, two levels of "
+                        "192 + 64 planes (7x7 low level, 9x9 centre crop)",
+            "plain_f32_ms_per_batch": plain, "batched_ms_per_batch": batched,
+            "batched_form": "persistent launch, FP16 staging, HIP graph", "autotuned": choice,
+            "maps_per_s_plain": 16e3 / plain, "maps_per_s_batched": 16e3 / batched,
+            "gpix_planes_per_s_batched": pp5 / (batched * 1e-3) / 1e9, "ratio": plain / batched}
     if args.copy_calibration:
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -92,6 +92,8 @@ def lib():
                            _p, _p, _p, _p]
     L.or_merge.restype = None
     L.or_soft_forward.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i64, _p, _p, _p]
+    L.or_soft_argmin.argtypes = [_p, _p, _i32, _d, _p, _p]
+    L.or_soft_argmin.restype = None
     L.or_soft_forward.restype = None
     L.or_soft_backward.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i32, _i32, _i32, _i32, _p, _p, _p]
     L.or_soft_backward.restype = None
@@ -359,6 +361,17 @@ def _src_arrays(src_cams, src_imgs, poses):
     Ss = [_Img(s) for s in src_imgs]
     return (Ss, (OrImage * S)(*[s.s for s in Ss]), (OrCamera * S)(*[camera(c) for c in src_cams]),
             (OrPose * S)(*[pose(p) for p in poses]))
+
+
+def soft_argmin(costs, rhos, temperature):
+    """Soft-argmin of one pixel: costs C_k (NaN = unusable plane) and plane
+    parameters rho_k -> (rho_hat, lse) with p = softmax(-C / T)."""
+    C = np.ascontiguousarray(costs, np.float64)
+    r = np.ascontiguousarray(rhos, np.float64)
+    rh, lse = ctypes.c_double(), ctypes.c_double()
+    lib().or_soft_argmin(C.ctypes.data, r.ctypes.data, len(C), float(temperature), ctypes.byref(rh),
+                         ctypes.byref(lse))
+    return rh.value, lse.value
 
 
 def soft_forward(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, pixels=None):

@@ -492,10 +492,34 @@ void or_merge(const or_camera *full, const or_params *p0, const or_params *p1,
 /* ------------------------------------------------------------------------ */
 
 /*
- * Soft-argmin inverse depth (no counterpart in the paper; the hypotheses are
- * the paper's fronto planes): with l_k = -C_k / T over the valid planes,
- * p = softmax(l) and rho_hat = sum_k p_k rho_k.  lse = log sum_k exp(l_k).
- * Pixels without a valid plane give rho_hat = NaN and lse = -inf.
+ * Soft-argmin of one pixel (no counterpart in the paper; the hypotheses are
+ * the paper's fronto planes): with l_k = -C_k / T over the valid planes (C_k
+ * not NaN), p = softmax(l) and rho_hat = sum_k p_k rho_k, lse = log sum_k
+ * exp(l_k), both computed with the largest l_k taken out.  No valid plane:
+ * rho_hat = NaN and lse = -inf.
+ */
+void or_soft_argmin(const double *C, const double *rho, int32_t P, double T, double *rho_hat, double *lse)
+{
+    double m = -INFINITY;
+    for (int k = 0; k < P; ++k)
+        if (!isnan(C[k]) && -C[k] / T > m) m = -C[k] / T;
+    if (isinf(m)) {
+        *rho_hat = NAN; *lse = -INFINITY;
+        return;
+    }
+    double se = 0, sr = 0;
+    for (int k = 0; k < P; ++k) {
+        if (isnan(C[k])) continue;
+        double ex = exp(-C[k] / T - m);
+        se += ex;
+        sr += ex * rho[k];
+    }
+    *rho_hat = sr / se;
+    *lse = m + log(se);
+}
+
+/*
+ * Soft-argmin inverse depth of every pixel over the fronto planes' costs.
  */
 void or_soft_forward(const or_params *p, const or_camera *rc, const or_image *ref, int32_t S,
                      const or_camera *scs, const or_image *srcs, const or_pose *poses,
@@ -507,23 +531,11 @@ void or_soft_forward(const or_params *p, const or_camera *rc, const or_image *re
         int i = pix ? pix[2 * e] : (int)(e % ref->width);
         int j = pix ? pix[2 * e + 1] : (int)(e / ref->width);
         double *C = (double *)malloc(sizeof(double) * P);
+        double *rho = (double *)malloc(sizeof(double) * P);
         pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, NULL, NULL);
-        double m = -INFINITY;
-        for (int k = 0; k < P; ++k)
-            if (!isnan(C[k]) && -C[k] / p->temperature > m) m = -C[k] / p->temperature;
-        if (isinf(m)) {
-            rho_hat[e] = NAN; lse[e] = -INFINITY;
-        } else {
-            double se = 0, sr = 0;
-            for (int k = 0; k < P; ++k) {
-                if (isnan(C[k])) continue;
-                double ex = exp(-C[k] / p->temperature - m);
-                se += ex;
-                sr += ex * or_plane_param(p, k, NULL);
-            }
-            rho_hat[e] = sr / se;
-            lse[e] = m + log(se);
-        }
+        for (int k = 0; k < P; ++k) rho[k] = or_plane_param(p, k, NULL);
+        or_soft_argmin(C, rho, P, p->temperature, &rho_hat[e], &lse[e]);
+        free(rho);
         free(C);
     }
 }

@@ -131,3 +131,22 @@ def test_image_gradient_matches_central_differences(frame):
             assert abs(fd - gs[s][j, i]) <= 1e-5 * max(1e-3, abs(fd)) + 1e-9, (s, j, i, fd, gs[s][j, i])
             checked += 1
     assert checked == 12
+
+
+def test_soft_argmin_golden():
+    """The soft-argmin step against the hand-computed closed-form values of
+    tests/golden/soft_argmin_hand.txt: a wrong temperature scale (exp(-C/2T)),
+    a dropped max shift or a sign error in lse moves these by far more than
+    the tolerance."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "soft_argmin_hand.txt")
+    rows = [l for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for row in rows:
+        T, C, rho, rh, lse = [f.split() for f in row.split("|")]
+        got_rh, got_lse = oracle.soft_argmin([float(c) for c in C], [float(r) for r in rho], float(T[0]))
+        want_rh, want_lse = float(rh[0]), float(lse[0])
+        if np.isnan(want_rh):
+            assert np.isnan(got_rh) and got_lse == -np.inf
+        else:
+            assert abs(got_rh - want_rh) <= 1e-14 and abs(got_lse - want_lse) <= 1e-14, (row, got_rh, got_lse)
