@@ -124,9 +124,37 @@ void or_tsdf_alloc(const ot_camera *cam, const ot_pose *pose, const double *dept
         }
 }
 
+/* FP32 error bounds of the decisions the GPU takes, for the parity tests'
+ * exclusion flags (no part of the fusion).  The GPU works on positions
+ * relative to the box's first block: with L = |X - origin| + |c - origin|
+ * (point and camera centre), the rigid transform's result is within
+ * 8 u L of the exact one per coordinate (u = 2^-24: three products and
+ * three sums of magnitude <= L, each rounded once); the range |X_d| and eta
+ * within 9 u L; a projection u = fx x / den + cx within
+ * fx 8 u L (1 + 2 |x / den|) / den + 4 u |u| (den = z + xi |X_d|, the quotient
+ * and the final FMA rounded once more).  The flags take four times these. */
+#define OT_U 5.9604644775390625e-8   /* 2^-24 */
+static double ot_lever(const ot_pose *pose, const double Xw[3], const double origin[3])
+{
+    /* |X - origin| + |camera centre - origin|, centre = -R^T t */
+    double c[3], mt[3] = {-pose->t[0], -pose->t[1], -pose->t[2]};
+    for (int i = 0; i < 3; ++i) c[i] = pose->R[0 * 3 + i] * mt[0] + pose->R[1 * 3 + i] * mt[1] + pose->R[2 * 3 + i] * mt[2];
+    double a = 0, b = 0;
+    for (int i = 0; i < 3; ++i) { a += (Xw[i] - origin[i]) * (Xw[i] - origin[i]); b += (c[i] - origin[i]) * (c[i] - origin[i]); }
+    return sqrt(a) + sqrt(b);
+}
+static double ot_proj_margin(const ot_camera *cam, const double Xc[3], double u, double f, double c, double L)
+{
+    const double m = sqrt(Xc[0] * Xc[0] + Xc[1] * Xc[1] + Xc[2] * Xc[2]);
+    const double den = Xc[2] + cam->xi * m;
+    const double r = fabs(u - c) / f;   /* |x / den| */
+    return 4.0 * (f * 8.0 * OT_U * L * (1.0 + 2.0 * r) / den + 4.0 * OT_U * (fabs(u) + 1.0));
+}
+
 /* Step 2.  vis[nb]: allocated blocks with a corner that projects into
  * [0, W-1] x [0, H-1].  edge[nb]: 1 where a corner projection lies within
- * 1e-2 px of that border (a decision FP32 arithmetic may take the other way). */
+ * its FP32 error bound of that border (a decision FP32 arithmetic may take
+ * the other way). */
 void or_tsdf_visible(const ot_camera *cam, const ot_pose *pose, double voxel, const int32_t b0[3],
                      const int32_t nb[3], const int32_t *alloc, int32_t *vis, int32_t *edge)
 {
@@ -145,16 +173,19 @@ void or_tsdf_visible(const ot_camera *cam, const ot_pose *pose, double voxel, co
                     to_cam(pose, Xw, Xc);
                     if (!or_project(cam, Xc, &u, &v)) continue;
                     double m = fmin(fmin(u, cam->width - 1 - u), fmin(v, cam->height - 1 - v));
-                    if (fabs(m) < 1e-2) edge[i] = 1;
+                    const double origin[3] = {b0[0] * B, b0[1] * B, b0[2] * B};
+                    const double L = ot_lever(pose, Xw, origin);
+                    const double tol = fmax(ot_proj_margin(cam, Xc, u, cam->fx, cam->cx, L),
+                                            ot_proj_margin(cam, Xc, v, cam->fy, cam->cy, L));
+                    if (fabs(m) < tol) edge[i] = 1;
                     if (m >= 0.0) vis[i] = 1;
                 }
             }
 }
 
 /* Step 3 (Eq. (2)).  D, W over the box's voxel grid.  edge_vox: 1 where the
- * voxel's update is decided within FP32 rounding of the pixel choice (a
- * projection within 2e-3 px of a pixel boundary) or of the eta >= -mu test
- * (within 1e-3 m). */
+ * voxel's update is decided within the FP32 error bound of the pixel choice
+ * (a projection that close to a pixel boundary) or of the eta >= -mu test. */
 void or_tsdf_integrate(const ot_camera *cam, const ot_pose *pose, const double *depth, int64_t pitch, double voxel,
                        double mu, double w_max, const int32_t b0[3], const int32_t nb[3], const int32_t *vis,
                        double *D, double *W, int32_t *edge_vox)
@@ -173,15 +204,19 @@ void or_tsdf_integrate(const ot_camera *cam, const ot_pose *pose, const double *
                 to_cam(pose, Xw, Xc);
                 if (!or_project(cam, Xc, &u, &v)) continue;
                 double fu = floor(u + 0.5), fv = floor(v + 0.5);
-                if (fabs(u + 0.5 - fu) < 2e-3 || fabs(u + 0.5 - fu - 1.0) < 2e-3 ||
-                    fabs(v + 0.5 - fv) < 2e-3 || fabs(v + 0.5 - fv - 1.0) < 2e-3)
+                const double origin[3] = {(double)b0[0] * 8 * voxel, (double)b0[1] * 8 * voxel, (double)b0[2] * 8 * voxel};
+                const double L = ot_lever(pose, Xw, origin);
+                const double tu = ot_proj_margin(cam, Xc, u, cam->fx, cam->cx, L);
+                const double tv = ot_proj_margin(cam, Xc, v, cam->fy, cam->cy, L);
+                if (fabs(u + 0.5 - fu) < tu || fabs(u + 0.5 - fu - 1.0) < tu ||
+                    fabs(v + 0.5 - fv) < tv || fabs(v + 0.5 - fv - 1.0) < tv)
                     edge_vox[o] = 1;
                 if (fu < 0 || fv < 0 || fu > cam->width - 1 || fv > cam->height - 1) continue;
                 double d_obs = depth[(int64_t)fv * pitch + (int64_t)fu];
                 if (!(d_obs > 0.0) || !isfinite(d_obs)) continue;
                 double range = sqrt(Xc[0] * Xc[0] + Xc[1] * Xc[1] + Xc[2] * Xc[2]);
                 double eta = d_obs - range;
-                if (fabs(eta + mu) < 1e-3) edge_vox[o] = 1;
+                if (fabs(eta + mu) < 4.0 * 9.0 * OT_U * L) edge_vox[o] = 1;
                 if (eta < -mu) continue;
                 double f = eta / mu < 1.0 ? eta / mu : 1.0;
                 D[o] = (W[o] * D[o] + f) / (W[o] + 1.0);

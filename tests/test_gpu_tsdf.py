@@ -12,6 +12,13 @@ pytestmark = pytest.mark.gpu
 VOX, MU = 0.1, 0.3
 
 
+def _pen_tol(blocks):
+    """Depth below which a segment's reach into a block is within FP32 error:
+    4 x 8 u L with u = 2^-24 and L twice the box's diagonal (metres)."""
+    L = 2.0 * np.linalg.norm(np.asarray(blocks, float) * 8 * VOX)
+    return 4.0 * 8.0 * 2.0 ** -24 * L
+
+
 def _gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -19,7 +26,7 @@ def _gpu():
     return TsdfMap
 
 
-def _margin_masks(infos):
+def _margin_masks(infos, pen_tol):
     """Voxels whose oracle decisions sit on an FP32-sensitive boundary in any
     fused frame: grazed blocks, corner projections on the image border,
     nearest-pixel ties and eta at -mu.  The flags of earlier frames move with
@@ -34,7 +41,10 @@ def _margin_masks(infos):
             bad_blk = oracle.tsdf_shift(bad_blk, sh, 1, False)
             bad_vox = oracle.tsdf_shift(bad_vox, sh, 8, False)
         b0 = inf["b0"]
-        bad_blk |= (inf["touched"] == 1) & (inf["pen"] < 1e-3)
+        # a segment that reaches into a block no deeper than the FP32 error of
+        # the GPU's box-relative positions (8 u L per coordinate, u = 2^-24,
+        # L = twice the box's diagonal; four times that) is taken either way
+        bad_blk |= (inf["touched"] == 1) & (inf["pen"] < pen_tol)
         bad_blk |= inf["vis_edge"] == 1
         bad_vox |= inf["voxel_edge"] == 1
     up = np.repeat(np.repeat(np.repeat(bad_blk, 8, 0), 8, 1), 8, 2)
@@ -60,7 +70,8 @@ def test_tsdf_matches_oracle(blocks, steps, shift):
     torch.cuda.synchronize()
     g_d, g_w, g_c = out["tsdf"].cpu().numpy(), out["weight"].cpu().numpy(), out["count"].cpu().numpy()
     assert np.array_equal(out["first_block"], o.b0)
-    bad_blk, bad_vox = _margin_masks(infos)
+    bad_blk, bad_vox = _margin_masks(infos, _pen_tol(blocks))
+    print("excluded blocks", bad_blk.mean(), "voxels", bad_vox.mean())
     # block observation counts
     ok = ~bad_blk
     assert np.array_equal(g_c[ok], o.count[ok]), (g_c[ok] != o.count[ok]).sum()
