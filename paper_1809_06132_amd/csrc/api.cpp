@@ -26,8 +26,9 @@ extern "C" const void *psw_chunk_merge_kernel();
 extern "C" const void *psw_filter_kernel();
 extern "C" const void *psw_mask_kernel();
 extern "C" const void *psw_backward_kernel(int win, int n_src, int img, int image_grads);
-extern "C" size_t psw_backward_lds(int win, int n_src);
+extern "C" size_t psw_backward_lds(int win, int n_src, int image_grads);
 extern "C" int psw_backward_tile_rows();
+extern "C" int psw_backward_threads(int image_grads);
 extern "C" const void *psw_zero_kernel();
 extern "C" const void *psw_pose_reduce_kernel();
 extern "C" hipError_t psw_static_scratch(void **ptr, size_t *bytes);
@@ -1127,7 +1128,7 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     for (int s = 0; s < C.n_src; ++s) any_image |= gsrc[s] != nullptr;
     const void *bk = psw_backward_kernel(win, C.n_src, ctx->cfg.image_format, any_image ? 1 : 0);
     if (!bk) return fail(ctx, PSWEEP_EUNSUPPORTED, "no backward kernel for this window / source count");
-    const size_t lds = psw_backward_lds(win, C.n_src);
+    const size_t lds = psw_backward_lds(win, C.n_src, any_image ? 1 : 0);
     if (lds > 65536) PSW_HIP(hipFuncSetAttribute(bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds limit");
     const int hw = win / 2;
     const int w = C.ref.width, h = C.ref.height;
@@ -1139,7 +1140,8 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     // gradient is independent given rho_hat and lse): about 24 waves per
     // SIMD, at least two planes per chunk
     const int nf = ctx->cfg.level[0].n_fronto;
-    int nch = tiles ? (int)((24LL * ctx->n_cu * 4 + 4LL * tiles - 1) / (4LL * tiles)) : 1;
+    const long long wpg = psw_backward_threads(any_image ? 1 : 0) / kWave;   // waves per workgroup
+    int nch = tiles ? (int)((24LL * ctx->n_cu * 4 + wpg * tiles - 1) / (wpg * tiles)) : 1;
     nch = std::max(1, std::min(std::min(nch, 16), std::max(1, nf / 2)));
     // the pose gradient: one partial row of 6 S doubles per workgroup, in the
     // plane-chunk region of the soft run (merged by then), summed in order
@@ -1154,7 +1156,8 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
         int64_t sp = ctx->soft_pitch;
         void *a[] = {(void *)&job, (void *)&d_grad_invdepth, (void *)&rho, (void *)&lse, &sp,
                      &g0, &g1, &g2, &g3, &gpart};
-        PSW_HIP(hipLaunchKernel(bk, dim3(tx, ty, nch), dim3(256), a, lds, stream), "backward");
+        PSW_HIP(hipLaunchKernel(bk, dim3(tx, ty, nch), dim3(psw_backward_threads(any_image ? 1 : 0)), a, lds, stream),
+                "backward");
     }
     {
         int nr = n_rows, np = n_pose;

@@ -14,13 +14,38 @@
 // (transposed box) sum over the pixels whose window holds q:
 //   dL/db_q = a_q sum(G/D) - sum(G abar/D) - b_q sum(G Z/s_bb) + sum(G Z bbar/s_bb).
 // Each sample's gradient then goes through the bilinear interpolant to the
-// four source texels (atomics) and through the projection to the pose.
+// four source texels and through the projection to the pose.
 //
-// Tile layout: 4 waves, lane = sample column, 4 output rows per wave.  Per
-// output pixel the channels G/D, G Z/s_bb and G Z bbar/s_bb of every source
-// and the reference mean abar (shared by the sources; sum(G abar/D) is formed
-// from G/D and abar while summing) take 28 KB of LDS for two sources, so four
-// workgroups share a CU.  Every wave owns a contiguous
+// Image gradient: a workgroup sweeps one chunk of consecutive planes, and
+// between neighbouring planes its tile's footprint in a source moves only by
+// the parallax of one plane step.  Each source gets an LDS patch of the source
+// image placed over the footprint of the whole chunk (from a few probe
+// samples warped at the chunk's first and last plane); the taps land there as
+// LDS atomics, and at the end the patch goes to the gradient image with one
+// global atomic per touched texel.  A sample whose taps fall outside the
+// patch adds them to the gradient image directly.
+//
+// The patch holds 64-bit fixed-point sums: LDS float atomics are slow next
+// to the rest of the loop (about one lane every two clocks per CU), integer
+// ones are not.  The workgroup's scale 2^F follows from a bound on every tap:
+// with |a_q - abar| <= sqrt(s_aa), |b_q - bbar| <= sqrt(s_bb), |Z| < 1 and
+// s_bb above the variance floor, |dL/db_q| <= N max|g| (theta range) /
+// (T sqrt(floor)), and a texel takes at most 4 taps of each sample of the
+// tile on each plane of the chunk; F leaves that total below 2^61 (times a
+// safety factor of 4 for FP32 rounding).  Below a floor of 1/16 grey^2 per
+// pixel FP32 cancellation in s_bb can exceed the bound, so there (and for a
+// bound that is not finite) every tap goes to the gradient image directly.
+// Before the atomics, the taps neighbouring samples share are folded
+// together in registers: a lane's bottom taps with the same lane's top taps
+// of the next sample row, and a lane's right taps with the left taps of the
+// lane to its right, about one atomic per sample at unit scale instead of
+// four.
+//
+// Tile layout: 16 output rows, lane = sample column, 8 waves of 2 output
+// rows.  Per output pixel the channels G/D,
+// G Z/s_bb and G Z bbar/s_bb of every source and the reference mean abar
+// (shared by the sources; sum(G abar/D) is formed from G/D and abar while
+// summing) take 28 KB of LDS for two sources.  Every wave owns a contiguous
 // block of the tile's sample rows: it warps them into LDS, and after the
 // channels are written it walks down the block keeping running sums of the
 // channels over the output rows whose window holds the current sample row
@@ -48,15 +73,33 @@ __device__ __forceinline__ void gadd(__amdgpu_buffer_rsrc_t rs, int off, float v
     __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(v, rs, off, 0, 0);
 }
 
+// fixed-point atomic add to a 64-bit sum in LDS (no return): v times the
+// scale, truncated (|v * scale| < 2^61)
+__device__ __forceinline__ void ladd(unsigned long long *p, float v, float scale) {
+    __hip_atomic_fetch_add(p, (unsigned long long)(long long)(v * scale), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// minimum over the wave
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
 __global__ void zero_kernel(float *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0f;
 }
 
-// GI: whether any source's image gradient is wanted (false: pose only)
+// GI: whether any source's image gradient is wanted (false: pose only).
+// Tiles of 16 output rows, 8 waves of 2 output rows: two workgroups with
+// their patches fill a CU with 16 waves.  The pose-only form has the same
+// shape, so that its pose gradient is summed in the same order, bit for bit
+// the one of the full form.
 template <int WIN, int S, int IMG, bool GI>
 struct Backward {
-    static constexpr int NW = 4, R = 4;
+    static constexpr int NW = 8, R = 2;
     static constexpr int HW = WIN / 2;
     static constexpr int TXO = kWave - 2 * HW;
     static constexpr int TYO = NW * R;
@@ -65,8 +108,15 @@ struct Backward {
     static constexpr int VR = R + 2 * HW;
     static constexpr int NCH = 3;   // channels per source; plus one plane of abar
 
+    // image-gradient patch of each source: PH rows of PW texels (the tile's
+    // 64 x T samples, plus the parallax of a chunk's planes and a margin)
+    static constexpr int PW = 80, PH = T + 8;
+
     static constexpr size_t lds_tile() { return (size_t)S * T * kWave * 4; }
-    static constexpr size_t lds_bytes() { return lds_tile() + (size_t)(NCH * S + 1) * TYO * kWave * 4; }
+    static constexpr size_t lds_patch() { return GI ? (size_t)S * PH * PW * 8 : 0; }
+    static constexpr size_t lds_bytes() {
+        return lds_tile() + (size_t)(NCH * S + 1) * TYO * kWave * 4 + lds_patch();
+    }
 
     __device__ static void run(const JobDev *__restrict__ Jp, const float *__restrict__ gin,
                                const float *__restrict__ rho_hat, const float *__restrict__ lse, int64_t spitch,
@@ -75,6 +125,11 @@ struct Backward {
         float *tile = reinterpret_cast<float *>(smem);
         float *chan = tile + (size_t)S * T * kWave;   // [s][c][output row][lane]
         float *abar = chan + (size_t)NCH * S * TYO * kWave;   // [output row][lane]
+        // [s][PH][PW] fixed-point sums (GI); 8-byte aligned (the regions
+        // before it are multiples of 256 bytes)
+        unsigned long long *patch = reinterpret_cast<unsigned long long *>(abar + (size_t)TYO * kWave);
+        __shared__ int porg[2 * kMaxSrc];                      // patch origin (column, row) per source
+        __shared__ float gmax_w[NW], theta_rng;                // per-wave max |g|, theta range
         const int lane = threadIdx.x & (kWave - 1);
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
         const int W = J.w, H = J.h;
@@ -149,6 +204,13 @@ struct Backward {
                 }
             }
         }
+        if constexpr (GI) {
+            float gm = 0.0f;
+#pragma unroll
+            for (int i = 0; i < R; ++i) gm = fmaxf(gm, __builtin_fabsf(gp[i]));
+            gm = -wave_min(-gm);
+            if (lane == 0) gmax_w[wave] = gm;
+        }
         // the reference means of this wave's output rows, for every plane
 #pragma unroll
         for (int i = 0; i < R; ++i) abar[(size_t)(wave * R + i) * kWave + lane] = mean_a[i];
@@ -166,6 +228,77 @@ struct Backward {
         const int nchunk = (int)gridDim.z, chunk = (int)blockIdx.z;
         const int k_lo = (int)((int64_t)chunk * J.n_fronto / nchunk);
         const int k_hi = (int)((int64_t)(chunk + 1) * J.n_fronto / nchunk);
+        if constexpr (GI) {
+            for (int t = threadIdx.x; t < S * PH * PW; t += NW * kWave) patch[t] = 0ull;
+            if (wave == 1) {
+                // range of the plane parameters (rho_hat lies within it)
+                float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+                for (int k = lane; k < J.n_fronto; k += kWave) {
+                    const float th = J.theta[k];
+                    lo = fminf(lo, th); hi = fmaxf(hi, th);
+                }
+                lo = wave_min(lo); hi = -wave_min(-hi);
+                if (lane == 0) theta_rng = hi - lo;
+            }
+            if (wave == 0) {
+                // probes: 3 x 3 sample positions of the tile at the chunk's
+                // first and last plane, 18 lanes per source
+                const int s = lane / 18, p = lane - 18 * (lane / 18), q = p % 9;
+                float u = __builtin_nanf(""), v = __builtin_nanf("");
+                if (s < S && k_hi > k_lo) {
+                    const int k = p < 9 ? k_lo : k_hi - 1;
+                    const int pc = blockIdx.x * TXO + (q % 3) * (kWave / 2 - 1) + (q % 3) / 2;   // 0, 31, 63
+                    const int pr = sr0 + (q / 3) * ((T - 1) / 2) + (q / 3) / 2 * ((T - 1) % 2);
+                    const float px_ = ((float)pc - J.cx) * J.inv_fx, py_ = ((float)pr - J.cy) * J.inv_fy;
+                    const float t = ray_tau(px_, py_, xi, nullptr);
+                    const float *hm = J.htab + (k * S + s) * 9;
+                    const float X = fmaf(hm[6], t, fmaf(hm[3], py_, hm[0] * px_));
+                    const float Y = fmaf(hm[7], t, fmaf(hm[4], py_, hm[1] * px_));
+                    const float Z = fmaf(hm[8], t, fmaf(hm[5], py_, hm[2] * px_));
+                    const SrcDev &sd = J.src[s];
+                    const float den = fmaf(sd.xi, __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z))), Z);
+                    if (t > 0.0f && den > 0.0f) {
+                        u = fmaf(X / den, sd.fx, sd.cx);
+                        v = fmaf(Y / den, sd.fy, sd.cy);
+                    }
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2) {
+                    const bool mine = s == s2 && u == u && v == v;
+                    const float inf = __builtin_huge_valf();
+                    const float u0 = wave_min(mine ? u : inf), u1 = -wave_min(mine ? -u : inf);
+                    const float v0 = wave_min(mine ? v : inf), v1 = -wave_min(mine ? -v : inf);
+                    int ox = 0, oy = 0;
+                    if (u0 < inf) {
+                        // the taps of the probes span columns floor(u0) .. floor(u1) + 1;
+                        // centre that span (clamped to the float range of ints) in the patch
+                        const float cu = fminf(fmaxf(0.5f * (u0 + u1), -1.0e9f), 1.0e9f);
+                        const float cv = fminf(fmaxf(0.5f * (v0 + v1), -1.0e9f), 1.0e9f);
+                        ox = (int)floorf(cu) - PW / 2;
+                        oy = (int)floorf(cv) - PH / 2;
+                    }
+                    if (lane == 0) { porg[2 * s2] = ox; porg[2 * s2 + 1] = oy; }
+                }
+            }
+        }
+        float scale = 0.0f;   // 2^F of the fixed-point patch sums; 0: no patch
+        if constexpr (GI) {
+            __syncthreads();
+            float gm = 0.0f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) gm = fmaxf(gm, gmax_w[w]);
+            // bound on the sum of one texel's taps (times 4), then F so that
+            // it stays below 2^61
+            const float per_tap = (float)(WIN * WIN) * gm * theta_rng /
+                                  (J.temperature * __builtin_sqrtf(J.var_floor_n));
+            const float total = 4.0f * per_tap * (float)(4 * (k_hi - k_lo) * T * kWave);
+            const bool ok = J.var_floor_n >= (float)(WIN * WIN) * 0.0625f && total < 1.0e30f;
+            if (ok) {
+                int e;
+                (void)frexpf(fmaxf(total, 1.0e-30f), &e);   // total < 2^e
+                scale = ldexpf(1.0f, min(61 - e, 126));
+            }
+        }
         for (int k = k_lo; k < k_hi; ++k) {
             const float theta = cptr(J.theta)[k];
             // ---- forward recompute: warped rows of every source into LDS ----
@@ -304,8 +437,12 @@ struct Backward {
                 }
                 // pose terms of this plane in FP32 (at most RS per lane), then FP64
                 float ps[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                // bottom taps carried down from the previous sample row of this
-                // lane: byte offset (-1: none) and value of (v1, i0) and (v1, i1)
+                int pox = 0, poy = 0;
+                unsigned long long *pat = patch + (size_t)s * PH * PW;
+                if (GI) { pox = porg[2 * s]; poy = porg[2 * s + 1]; }
+                if (GI && scale == 0.0f) { pox = -(1 << 30); poy = -(1 << 30); }   // every tap direct
+                // patch taps carried down from the previous sample row of this
+                // lane: patch index (-1: none) and value of (v1, i0) and (v1, i1)
                 int ca0 = -1, ca1 = -1;
                 float cv0 = 0.f, cv1 = 0.f;
 #pragma unroll
@@ -329,9 +466,8 @@ struct Backward {
                     const float sC = wsum<WIN>(rC, sh), sE = wsum<WIN>(rE, sh);
                     const float b = tile[((size_t)s * T + j) * kWave + lane];
                     const float gb = fmaf(aw[i], sA, -sB) + fmaf(-b, sC, sE);
-                    // the four bilinear taps of this sample: byte offset of the
-                    // texel in the gradient image (-1: none) and gradient, order
-                    // (v0, i0), (v0, i1), (v1, i0), (v1, i1)
+                    // this sample's patch taps (v0, i0), (v0, i1), (v1, i0), (v1, i1):
+                    // patch index (-1: none) and gradient
                     int a00 = -1, a10 = -1, a01 = -1, a11 = -1;
                     float c00 = 0.f, c10 = 0.f, c01 = 0.f, c11 = 0.f;
                     if ((gb != 0.0f) & !is_neg_zero(b)) {
@@ -351,12 +487,22 @@ struct Backward {
                         float dbu, dbv;
                         Texel<IMG>::slope(rs, __umul24((uint32_t)v0, row_bytes) + (uint32_t)i0 * Texel<IMG>::bytes, al, be,
                                           &dbu, &dbv);
-                        a00 = (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i0 * 4u);
-                        a10 = (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i1 * 4u);
-                        a01 = (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i0 * 4u);
-                        a11 = (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i1 * 4u);
-                        c00 = gb * (1.0f - al) * (1.0f - be); c10 = gb * al * (1.0f - be);
-                        c01 = gb * (1.0f - al) * be; c11 = gb * al * be;
+                        if (GI && gimg) {
+                            c00 = gb * (1.0f - al) * (1.0f - be); c10 = gb * al * (1.0f - be);
+                            c01 = gb * (1.0f - al) * be; c11 = gb * al * be;
+                            const int pi = i0 - pox, pj = v0 - poy;
+                            if ((uint32_t)pi < (uint32_t)(PW - 1) && (uint32_t)pj < (uint32_t)(PH - 1)) {
+                                a00 = pj * PW + pi;
+                                a10 = a00 + (i1 - i0);
+                                a01 = a00 + (v1 - v0) * PW;
+                                a11 = a01 + (i1 - i0);
+                            } else {
+                                gadd(grs, (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i0 * 4u), c00);
+                                gadd(grs, (int)(__umul24((uint32_t)v0, grow) + (uint32_t)i1 * 4u), c10);
+                                gadd(grs, (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i0 * 4u), c01);
+                                gadd(grs, (int)(__umul24((uint32_t)v1, grow) + (uint32_t)i1 * 4u), c11);
+                            }
+                        }
                         // (X, Y, Z) = H (x, y, tau) is the source point P divided by
                         // sigma = 1 / (theta tau) (fronto planes).  With
                         // xu = X / den, yv = Y / den, Au = dbu fx / den,
@@ -378,33 +524,31 @@ struct Backward {
                         ps[4] = fmaf(gb, fmaf(Z, e0, -X * e2), ps[4]);
                         ps[5] = fmaf(gb, fmaf(X, e1, -Y * e0), ps[5]);
                     }
-                    if (GI && gimg) {   // image gradient requested for this source
-                        // Neighbouring samples of a near-unit-scale warp share
-                        // taps: fold them together before the atomics.
-                        // (a) this lane's bottom taps of the previous row are
-                        // this row's top taps (same texel row and columns)
+                    if (GI && gimg) {
+                        // (a) this lane's bottom taps of the previous row are this
+                        // row's top taps (same texel row and columns)
                         if (ca0 >= 0 && ca0 == a00) {
                             c00 += cv0;
-                            c10 += cv1;   // ca1 is a10 or was handed on (cv1 = 0)
+                            c10 += cv1;   // ca1 is a10, or was handed on (cv1 = 0)
                         } else {
-                            if (ca0 >= 0) gadd(grs, ca0, cv0);
-                            if (ca1 >= 0) gadd(grs, ca1, cv1);
+                            if (ca0 >= 0) ladd(pat + ca0, cv0, scale);
+                            if (ca1 >= 0) ladd(pat + ca1, cv1, scale);
                         }
-                        // (b) the left lane's right taps are this lane's left
-                        // taps; the left lane then drops them
+                        // (b) the left lane's right taps are this lane's left taps;
+                        // the left lane then drops them
                         const int l10 = lane_shr1_i(a10, -1);
                         const float l10v = shr1(c10), l11v = shr1(c11);
                         if (a00 >= 0 && l10 == a00) { c00 += l10v; c01 += l11v; }
                         const bool handed = a10 >= 0 && lane_shl1_i(a00, -1) == a10;
-                        if (a00 >= 0) gadd(grs, a00, c00);
-                        if (a10 >= 0 && !handed) gadd(grs, a10, c10);
+                        if (a00 >= 0) ladd(pat + a00, c00, scale);
+                        if (a10 >= 0 && !handed) ladd(pat + a10, c10, scale);
                         ca0 = a01; cv0 = c01;
                         ca1 = handed ? -1 : a11; cv1 = handed ? 0.f : c11;
                     }
                 }
                 if (GI && gimg) {
-                    if (ca0 >= 0) gadd(grs, ca0, cv0);
-                    if (ca1 >= 0) gadd(grs, ca1, cv1);
+                    if (ca0 >= 0) ladd(pat + ca0, cv0, scale);
+                    if (ca1 >= 0) ladd(pat + ca1, cv1, scale);
                 }
 #pragma unroll
                 for (int a = 0; a < 3; ++a) acc[s][a] = fmaf(ps[a], theta, acc[s][a]);
@@ -412,6 +556,29 @@ struct Backward {
                 for (int a = 3; a < 6; ++a) acc[s][a] += ps[a];
             }
             __syncthreads();
+        }
+        // ---- image gradient: the patches to the gradient images, one atomic
+        // per touched texel (a texel is touched only by in-image taps) ----
+        if constexpr (GI) {
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                float *gimg = gsrc[s];
+                if (!gimg) continue;
+                const SrcDev &sd = J.src[s];
+                const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+                    gimg, (short)0, (int)((uint32_t)sd.w * (uint32_t)sd.h * 4u), 0x00020000);
+                const int pox = porg[2 * s], poy = porg[2 * s + 1];
+                const unsigned long long *pat = patch + (size_t)s * PH * PW;
+                const float inv_scale = scale > 0.0f ? 1.0f / scale : 0.0f;   // a power of two
+                for (int t = threadIdx.x; t < PH * PW; t += NW * kWave) {
+                    const long long q = (long long)pat[t];
+                    if (q != 0) {
+                        const int pj = t / PW, pi = t - pj * PW;
+                        gadd(grs, ((poy + pj) * sd.w + pox + pi) * 4, (float)q * inv_scale);
+                    }
+                }
+            }
         }
         // ---- pose gradient: wave reduction, then the workgroup's partial sum
         // (one row of gpart per workgroup; a second kernel adds the rows in a
@@ -438,11 +605,11 @@ struct Backward {
 };
 
 template <int WIN, int S, int IMG, bool GI>
-__global__ __launch_bounds__(256) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
+__global__ __launch_bounds__((Backward<WIN, S, IMG, GI>::NW * kWave)) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
                                                         const float *__restrict__ rho, const float *__restrict__ lse,
                                                         int64_t spitch, float *g0, float *g1, float *g2, float *g3,
                                                         double *gpart) {
-    extern __shared__ char smem[];
+    extern __shared__ __attribute__((aligned(16))) char smem[];   // after the static LDS, 16-byte aligned
     float *gs[4] = {g0, g1, g2, g3};
     Backward<WIN, S, IMG, GI>::run(job, gin, rho, lse, spitch, gs, gpart, smem);
 }
@@ -486,15 +653,18 @@ const void *psw_backward_kernel(int win, int n_src, int img, int image_grads) {
 }
 
 int psw_backward_tile_rows() { return psw::Backward<5, 1, 0, true>::TYO; }
+int psw_backward_threads(int image_grads) {
+    return image_grads ? psw::Backward<5, 1, 0, true>::NW * psw::kWave : psw::Backward<5, 1, 0, false>::NW * psw::kWave;
+}
 
-size_t psw_backward_lds(int win, int n_src) {
-#define PSW_L(W)                                                       \
-    if (win == W) {                                                    \
-        if (n_src == 1) return psw::Backward<W, 1, 0, true>::lds_bytes();    \
-        if (n_src == 2) return psw::Backward<W, 2, 0, true>::lds_bytes();    \
-        if (n_src == 3) return psw::Backward<W, 3, 0, true>::lds_bytes();    \
+size_t psw_backward_lds(int win, int n_src, int image_grads) {
+#define PSW_L(W, G)                                                          \
+    if (win == W && (image_grads != 0) == G) {                               \
+        if (n_src == 1) return psw::Backward<W, 1, 0, G>::lds_bytes();       \
+        if (n_src == 2) return psw::Backward<W, 2, 0, G>::lds_bytes();       \
+        if (n_src == 3) return psw::Backward<W, 3, 0, G>::lds_bytes();       \
     }
-    PSW_L(5) PSW_L(7) PSW_L(9)
+    PSW_L(5, true) PSW_L(7, true) PSW_L(9, true) PSW_L(5, false) PSW_L(7, false) PSW_L(9, false)
 #undef PSW_L
     return 0;
 }

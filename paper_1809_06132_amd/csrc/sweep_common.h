@@ -742,7 +742,7 @@ struct Tile {
 // job's item order (largest first).
 template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0>
 __global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__restrict__ job) {
-    extern __shared__ char smem[];
+    extern __shared__ __attribute__((aligned(16))) char smem[];   // after the static LDS, 16-byte aligned
     const int tx = job->tiles_x;
     // Blocks go to the eight XCDs round-robin (block b to XCD b % 8), and
     // every XCD has a queue of items (its share of the tile rows, so that
@@ -801,7 +801,7 @@ __device__ __forceinline__ int opaque_lane() {
 template <int R, int NW, int S, int STORE>
 __global__ __launch_bounds__(kWave *NW) void sweep_persistent_kernel(const JobDev *__restrict__ jobs, int n_jobs,
                                                                      int n_items, int *counter) {
-    extern __shared__ char smem[];
+    extern __shared__ __attribute__((aligned(16))) char smem[];   // after the static LDS, 16-byte aligned
     __shared__ int item_s, job_s;
     (void)n_items;
     (void)counter;

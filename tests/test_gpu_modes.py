@@ -166,14 +166,17 @@ def test_soft_forward_matches_oracle():
 
 
 BWD_CASES = [
-    # (window, n_src, best_k, w, h, n_fronto, seed)
-    (5, 2, 2, 64, 48, 16, 4),
-    (7, 3, 2, 90, 70, 12, 5),
-    (9, 1, 1, 100, 60, 10, 6),
+    # (window, n_src, best_k, w, h, n_fronto, seed, var_floor)
+    (5, 2, 2, 64, 48, 16, 4, 1.0),
+    (7, 3, 2, 90, 70, 12, 5, 1.0),
+    (9, 1, 1, 100, 60, 10, 6, 1.0),
+    # a variance floor below 1/16: the image-gradient taps skip the
+    # fixed-point LDS patch and go to the gradient images directly
+    (7, 2, 2, 80, 60, 12, 7, 0.05),
 ]
 
 
-@pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"w{c[0]}_S{c[1]}_K{c[2]}_{c[3]}x{c[4]}")
+@pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"w{c[0]}_S{c[1]}_K{c[2]}_{c[3]}x{c[4]}_vf{c[7]}")
 def test_soft_backward_matches_oracle_gradient(case):
     """The GPU gradient of sum(g * rho_hat) against the oracle's FP64
     analytic gradient (itself pinned by central differences), for a dense
@@ -181,10 +184,10 @@ def test_soft_backward_matches_oracle_gradient(case):
     on a temporary device copy of the frame, followed by allocations: the
     wrapper holds the reference image that the backward reads again."""
     PlaneSweep, frame_to_device = _gpu()
-    win, S, K, W, H, nf, seed = case
+    win, S, K, W, H, nf, seed, vfloor = case
     fr = scenegen.random_small_frame(w=W, h=H, n_src=S, seed=seed, f=0.62 * W)
     lv = Level(n_fronto=nf, near=1.0, far=15.0, window=win)
-    st = Settings(levels=[lv], best_k=K, mode="soft", temperature=0.1, var_floor=1.0)
+    st = Settings(levels=[lv], best_k=K, mode="soft", temperature=0.1, var_floor=vfloor)
     ps = PlaneSweep(st, W, H, S)
     ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
     out = ps.alloc_outputs()
