@@ -55,7 +55,14 @@ template <> struct Stage<1> {
     // + 0 turns it into +0 and leaves every other value as it is
     static __device__ __forceinline__ T put(float v) { return (_Float16)v + (_Float16)0.0f; }
     static __device__ __forceinline__ T bad() { return (_Float16)-0.0f; }
-    static __device__ __forceinline__ float get(T v) { return (float)v; }
+    // one conversion, kept apart from the FMAs that use it: folded into them
+    // as mixed-precision FMAs, the row loop schedules with stalls on the
+    // window sums' lane shifts (about 10% slower than the BF16 form)
+    static __device__ __forceinline__ float get(T v) {
+        float f = (float)v;
+        asm("" : "+v"(f));
+        return f;
+    }
 };
 template <> struct Stage<2> {
     using T = uint16_t;   // bfloat16 bits, round to nearest even
@@ -740,8 +747,17 @@ struct Tile {
 // ---------------------------------------------------------------------------
 // One grid per (frame, level), one workgroup per (chunk, tile) item, in the
 // job's item order (largest first).
+// FP16 staging on the default tile (4 waves of 4 rows) with windows up to 9:
+// held to 128 VGPRs, four waves per SIMD, without spills (left alone, the
+// compiler takes a register more for some and settles for three waves).
+// The other kernels keep the compiler's choice: a cap changes their schedule
+// for the worse (measured on the persistent launch).
+template <int WIN, int R, int NW, int S, int STORE>
+constexpr int sweep_waves_per_eu() { return R == 4 && NW == 4 && WIN <= 9 && STORE == 1 ? 4 : 1; }
+
 template <int WIN, int R, int NW, int S, int STORE, bool SOFT, int IMG = 0>
-__global__ __launch_bounds__(kWave *NW) void sweep_grid_kernel(const JobDev *__restrict__ job) {
+__global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<WIN, R, NW, S, STORE>())))
+void sweep_grid_kernel(const JobDev *__restrict__ job) {
     extern __shared__ __attribute__((aligned(16))) char smem[];   // after the static LDS, 16-byte aligned
     const int tx = job->tiles_x;
     // Blocks go to the eight XCDs round-robin (block b to XCD b % 8), and
