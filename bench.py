@@ -53,17 +53,17 @@ def cpu_model() -> str:
 
 # HBM bytes per launch of the sweep kernel on the C2 workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
-# "python bench.py --steps 2 --warmup 1 --no-cpu --copy-calibration", each
-# scaled by what the same counter reads for a 256 MiB device copy (FETCH_SIZE
-# reads half the copied bytes, WRITE_SIZE all of them).  Valid only for the
-# kernel code they were taken on: a hash of the sources' code (comments and
-# whitespace left out) guards them.
+# "python bench.py --steps 2 --warmup 1 --no-cpu --no-batched --copy-calibration"
+# (the persistent sweep kernel of C2), each scaled by what the same counter
+# reads for a 256 MiB device copy (FETCH_SIZE reads half the copied bytes,
+# WRITE_SIZE all of them).  Valid only for the kernel code they were taken on:
+# a hash of the sources' code (comments and whitespace left out) guards them.
 COUNTED_TRAFFIC = {
-    "sources_sha256": "534ffff08fe04bbe4be23cc52abec473f129842586a2ae4866bf1f57b8f12202",
-    "fetch_kib": 65569.9, "write_kib": 186142.3, "fetch_scale": 262144.0 / 131086.3, "write_scale": 1.0,
+    "sources_sha256": "aa7d99199608c28565b7a1799fb1017cd9af6e1f92e7686da375a7b273a59b72",
+    "fetch_kib": 28933.2, "write_kib": 184081.4, "fetch_scale": 262144.0 / 131086.8, "write_scale": 1.0,
 }
 TRAFFIC_SOURCES = ["paper_1809_06132_amd/csrc/sweep_common.h", "paper_1809_06132_amd/csrc/psweep_internal.h",
-                   "paper_1809_06132_amd/csrc/inst_grid.hip", "paper_1809_06132_amd/csrc/api.cpp"]
+                   "paper_1809_06132_amd/csrc/inst_persistent.hip", "paper_1809_06132_amd/csrc/api.cpp"]
 
 
 def _code_only(text: str) -> str:
