@@ -240,6 +240,17 @@ psweep_status psweep_run_noalloc(psweep_ctx *ctx, const psweep_frame *frames, in
 psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_invdepth,
                                          float *const *d_grad_src, double *d_grad_pose, void *hip_stream);
 
+/* A source pose moved by the left perturbation xi = (v, omega) whose gradient
+ * psweep_soft_depth_backward returns: R' = Exp(omega) R, t' = Exp(omega) t + v,
+ * with Exp the rotation exponential (Rodrigues' formula, its series for
+ * |omega| < 1e-4), i.e. X_src -> Exp(omega) X_src + v, which is
+ * X_src + v + omega x X_src to first order.  Host memory, FP64: R and R_out
+ * row-major 3x3, t and t_out 3-vectors, xi 6 values (v then omega); R_out may
+ * alias R and t_out alias t.  No context or GPU needed.  EINVAL for a NULL
+ * pointer or a non-finite xi. */
+psweep_status psweep_perturb_pose(const double *R, const double *t, const double *xi, double *R_out,
+                                  double *t_out);
+
 /* Tile shape of the sweep kernel for one level: rows per wave (2, 4, 8 or
  * 16) and waves per workgroup (2, 4 or 8); 0, 0 restores the default.  Used
  * by the autotuner.  EINVAL for other values; psweep_run returns

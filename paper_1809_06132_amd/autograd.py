@@ -18,28 +18,19 @@ float sources to 8 bits for the forward and returns the gradient of the
 interpolated intensities (straight-through rounding)."""
 from __future__ import annotations
 
-import math
-
 import numpy as np
 import torch
 
+from . import psweep as P
 from .sweep import PlaneSweep
-
-
-def _rodrigues(w: np.ndarray) -> np.ndarray:
-    th = float(np.linalg.norm(w))
-    if th < 1e-300:
-        return np.eye(3)
-    a = w / th
-    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
-    return np.eye(3) + math.sin(th) * K + (1 - math.cos(th)) * K @ K
 
 
 def perturb_pose(R: np.ndarray, t: np.ndarray, xi: np.ndarray):
     """exp(xi) * T with xi = (v, omega): R' = Exp(omega) R, t' = Exp(omega) t + v
-    (first order: X_s + v + omega x X_s)."""
-    Rw = _rodrigues(np.asarray(xi[3:], np.float64))
-    return Rw @ R, Rw @ t + np.asarray(xi[:3], np.float64)
+    (first order: X_s + v + omega x X_s), computed by the library."""
+    Ro, to = P.psweep_perturb_pose(np.asarray(R, np.float64).ravel(), np.asarray(t, np.float64).ravel(),
+                                   np.asarray(xi, np.float64).ravel())
+    return np.asarray(Ro).reshape(3, 3), np.asarray(to)
 
 
 class _Pose:

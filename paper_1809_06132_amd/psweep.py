@@ -27,7 +27,8 @@ EXPORTS = ["psweep_create", "psweep_workspace_size", "psweep_set_workspace", "ps
            "psweep_set_crop", "psweep_run", "psweep_run_noalloc", "psweep_soft_depth_backward", "psweep_set_tile",
            "psweep_graph_capture", "psweep_graph_launch", "psweep_set_timing", "psweep_sweep_kernel_ms",
            "psweep_sweep_kernel_times", "psweep_set_chunks", "psweep_filter", "psweep_mask_boxes",
-           "psweep_plane_pixels", "psweep_plane_pixels_met", "psweep_destroy", "psweep_last_error", "psweep_version",
+           "psweep_plane_pixels", "psweep_plane_pixels_met", "psweep_perturb_pose", "psweep_destroy",
+           "psweep_last_error", "psweep_version",
            "psweep_tsdf_create", "psweep_tsdf_workspace_size", "psweep_tsdf_set_workspace", "psweep_tsdf_reset",
            "psweep_tsdf_integrate", "psweep_tsdf_extract", "psweep_tsdf_region", "psweep_tsdf_stats",
            "psweep_tsdf_last_error", "psweep_tsdf_destroy"]
@@ -124,6 +125,7 @@ def lib() -> ctypes.CDLL:
     L.psweep_sweep_kernel_times.argtypes = [_p, P(_d), _i32, P(_i32)]
     L.psweep_plane_pixels.argtypes = [_p, P(psweep_frame), _i32, P(_i64)]
     L.psweep_plane_pixels_met.argtypes = [_p, P(psweep_frame), _i32, P(_i64)]
+    L.psweep_perturb_pose.argtypes = [P(_d), P(_d), P(_d), P(_d), P(_d)]
     L.psweep_destroy.argtypes = [_p]
     L.psweep_destroy.restype = None
     L.psweep_last_error.argtypes = [_p]
@@ -259,6 +261,14 @@ def psweep_plane_pixels_met(ctx, frames) -> int:
     c = _i64()
     _check(lib().psweep_plane_pixels_met(ctx, fa, n, ctypes.byref(c)), ctx)
     return c.value
+
+
+def psweep_perturb_pose(R, t, xi):
+    """(R', t') = (Exp(omega) R, Exp(omega) t + v) for xi = (v, omega), in FP64."""
+    Ra, ta, xa = (_d * 9)(*[float(v) for v in R]), (_d * 3)(*[float(v) for v in t]), (_d * 6)(*[float(v) for v in xi])
+    Ro, to = (_d * 9)(), (_d * 3)()
+    _check(lib().psweep_perturb_pose(Ra, ta, xa, Ro, to))
+    return list(Ro), list(to)
 
 
 def psweep_destroy(ctx):
