@@ -157,6 +157,10 @@ struct psweep_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t capture_stream = nullptr;
+    // grid launches of consecutive jobs alternate between the caller's stream
+    // and this one (default priority), forked and joined with events
+    hipStream_t side_stream = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::string err;
 };
 
@@ -341,6 +345,12 @@ psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out) {
         hipDeviceProp_t prop;
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
             ctx->n_cu = prop.multiProcessorCount;
+    }
+    if (hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
+        psweep_destroy(ctx);
+        return fail(nullptr, PSWEEP_EHIP, "stream or event creation failed");
     }
     // kernels with more than 64 KB of dynamic LDS need the limit raised
     for (const KernelEntry &e : all_kernels())
@@ -898,19 +908,41 @@ psweep_status enqueue(psweep_ctx *ctx, const Blob &blob, char *tb, int which, hi
         ctx->n_timed = 0;
     }
     if (cfg.launch == PSWEEP_LAUNCH_GRID) {
+        std::vector<const KernelEntry *> kern(nj, nullptr);
+        int n_launch = 0;
         for (int j = 0; j < nj; ++j) {
             const JobDev &J = (*host_jobs)[j];
-            const int ntile = J.tiles_x * J.tiles_y;
-            if (ntile == 0) continue;
-            const KernelEntry *e = find_kernel(J.window, J.rows, J.waves, J.n_src, store, soft, 0, cfg.image_format);
-            if (!e) return fail(ctx, PSWEEP_EUNSUPPORTED, "no kernel for this window/tile/sources/storage");
+            if (J.tiles_x * J.tiles_y == 0) continue;
+            kern[j] = find_kernel(J.window, J.rows, J.waves, J.n_src, store, soft, 0, cfg.image_format);
+            if (!kern[j]) return fail(ctx, PSWEEP_EUNSUPPORTED, "no kernel for this window/tile/sources/storage");
+            ++n_launch;
+        }
+        // Jobs share nothing they write (maps, partial states, queue
+        // counters are per job), so consecutive ones go to the caller's
+        // stream and the side stream in turn: a job's tail then overlaps the
+        // next job's start.  Both streams join the caller's before the merges.
+        const bool two = n_launch > 1 && ctx->side_stream;
+        if (two) {
+            PSW_HIP(hipEventRecord(ctx->fork_ev, stream), "fork event");
+            PSW_HIP(hipStreamWaitEvent(ctx->side_stream, ctx->fork_ev, 0), "fork wait");
+        }
+        int turn = 0;
+        for (int j = 0; j < nj; ++j) {
+            const JobDev &J = (*host_jobs)[j];
+            const KernelEntry *e = kern[j];
+            if (!e) continue;
+            const hipStream_t s = two && (turn++ & 1) ? ctx->side_stream : stream;
             JobDev *jp = dj + j;
             void *a[] = {&jp};
             // one block per (chunk, tile) item
-            const int grid = ntile * std::max(1, J.nch_f + J.nch_g);
-            if (timed) PSW_HIP(hipEventRecord(ctx->ev0[ctx->n_timed], stream), "event record");
-            PSW_HIP(hipLaunchKernel(e->fn, dim3(grid), dim3(kWave * J.waves), a, e->lds, stream), "sweep");
-            if (timed) PSW_HIP(hipEventRecord(ctx->ev1[ctx->n_timed++], stream), "event record");
+            const int grid = J.tiles_x * J.tiles_y * std::max(1, J.nch_f + J.nch_g);
+            if (timed) PSW_HIP(hipEventRecord(ctx->ev0[ctx->n_timed], s), "event record");
+            PSW_HIP(hipLaunchKernel(e->fn, dim3(grid), dim3(kWave * J.waves), a, e->lds, s), "sweep");
+            if (timed) PSW_HIP(hipEventRecord(ctx->ev1[ctx->n_timed++], s), "event record");
+        }
+        if (two) {
+            PSW_HIP(hipEventRecord(ctx->join_ev, ctx->side_stream), "join event");
+            PSW_HIP(hipStreamWaitEvent(stream, ctx->join_ev, 0), "join wait");
         }
     } else {
         int n_items = 0, n_src = (*host_jobs)[0].n_src;
@@ -1280,6 +1312,9 @@ void psweep_destroy(psweep_ctx *ctx) {
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     for (int b = 0; b < 2; ++b) {
         if (ctx->staging[b]) (void)hipHostFree(ctx->staging[b]);
         if (ctx->staging_ev[b]) (void)hipEventDestroy(ctx->staging_ev[b]);
