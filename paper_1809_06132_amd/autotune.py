@@ -17,7 +17,7 @@ import torch
 from .sweep import PlaneSweep
 
 CANDIDATES = [(4, 4), (8, 4), (4, 8), (2, 8), (16, 4), (8, 2)]
-CHUNK_CANDIDATES = [0, 1, 2, 4, 6, 8]     # 0: the library's automatic count
+CHUNK_CANDIDATES = [0, 1, 2, 3, 4, 6, 8]  # 0: the library's automatic count
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "psweep_tiles.json")
 
 

@@ -13,6 +13,9 @@ constexpr size_t persistent_lds() {
 #define PSW_P4(R, NW, ST) PSW_P(R, NW, 1, ST), PSW_P(R, NW, 2, ST), PSW_P(R, NW, 3, ST), PSW_P(R, NW, 4, ST)
 static const KernelEntry kPersistent[] = {
     PSW_P4(4, 4, 0), PSW_P4(4, 4, 1), PSW_P4(4, 4, 2), PSW_P4(8, 4, 0), PSW_P(8, 4, 4, 1),
+    // 8-wave tiles (fewer warped halo rows per output row); two workgroups
+    // fill a CU, except four sources in FP32 (80 KB of LDS), left out
+    PSW_P(4, 8, 3, 0), PSW_P(4, 8, 3, 1), PSW_P(4, 8, 3, 2), PSW_P(4, 8, 4, 1), PSW_P(4, 8, 4, 2),
 };
 }  // namespace psw
 

@@ -85,11 +85,15 @@ def _two_level_settings(w, h):
     ], best_k=2)
 
 
-@pytest.mark.parametrize("storage,n_src", [("f32", 4), ("f16", 4), ("bf16", 4), ("f32", 3)])
-def test_persistent_and_graph_match_grid(storage, n_src):
+@pytest.mark.parametrize("storage,n_src,ptile", [("f32", 4, (4, 4)), ("f16", 4, (4, 4)), ("bf16", 4, (4, 4)),
+                                                 ("f32", 3, (4, 4)), ("f32", 3, (4, 8)), ("bf16", 3, (4, 8)),
+                                                 ("f16", 4, (4, 8))])
+def test_persistent_and_graph_match_grid(storage, n_src, ptile):
     """Bitwise equal maps from the persistent launch, its graph replays and
-    the per-level grid launches, for every persistent kernel the batched
-    benchmarks use (three and four sources; FP32, FP16 and BF16 staging)."""
+    the per-level grid launches (default 4 x 4 tiles), for every persistent
+    kernel the batched benchmarks use (three and four sources; FP32, FP16 and
+    BF16 staging) and for persistent tiles of 8 waves of 4 rows (the same
+    per-pixel sums in the same order)."""
     PlaneSweep, frame_to_device = _gpu()
     sizes = [(256, 192), (200, 150), (160, 120)]
     frames = [scenegen._street_frame(w, h, 0.3516 * w, 7000 + i, 8000 + i, ss=1, extra_right=True)
@@ -109,6 +113,9 @@ def test_persistent_and_graph_match_grid(storage, n_src):
             d = frame_to_device(fr)
             d["camera_set"] = i
             dev.append(d)
+        if launch == "persistent":
+            for lv in range(len(st.levels)):
+                ps.set_tile(lv, *ptile)
         o = [ps.alloc_outputs(camera_set=i) for i in range(3)]
         ps.run(dev, o)
         torch.cuda.synchronize()
