@@ -62,7 +62,7 @@ typedef enum {
     PSWEEP_ESTATE = -2,        /* call out of order */
     PSWEEP_ENOMEM = -3,        /* host allocation failed or workspace too small */
     PSWEEP_EHIP = -4,          /* HIP runtime or launch error */
-    PSWEEP_EUNSUPPORTED = -5   /* valid request this build does not implement */
+    PSWEEP_EUNSUPPORTED = -5   /* valid request the library does not implement */
 } psweep_status;
 
 enum { PSWEEP_STORAGE_F32 = 0, PSWEEP_STORAGE_F16 = 1, PSWEEP_STORAGE_BF16 = 2 };
