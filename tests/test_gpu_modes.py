@@ -89,11 +89,11 @@ def _two_level_settings(w, h):
                                                  ("f32", 3, (4, 4)), ("f32", 3, (4, 8)), ("bf16", 3, (4, 8)),
                                                  ("f16", 4, (4, 8))])
 def test_persistent_and_graph_match_grid(storage, n_src, ptile):
-    """Bitwise equal maps from the persistent launch, its graph replays and
-    the per-level grid launches (default 4 x 4 tiles), for every persistent
-    kernel the batched benchmarks use (three and four sources; FP32, FP16 and
-    BF16 staging) and for persistent tiles of 8 waves of 4 rows (the same
-    per-pixel sums in the same order)."""
+    """Bitwise equal maps from the persistent launch, the graph replays of
+    both launches and the per-level grid launches (default 4 x 4 tiles), for
+    every persistent kernel the batched benchmarks use (three and four
+    sources; FP32, FP16 and BF16 staging) and for persistent tiles of 8 waves
+    of 4 rows (the same per-pixel sums in the same order)."""
     PlaneSweep, frame_to_device = _gpu()
     sizes = [(256, 192), (200, 150), (160, 120)]
     frames = [scenegen._street_frame(w, h, 0.3516 * w, 7000 + i, 8000 + i, ss=1, extra_right=True)
@@ -120,20 +120,21 @@ def test_persistent_and_graph_match_grid(storage, n_src, ptile):
         ps.run(dev, o)
         torch.cuda.synchronize()
         outs[launch] = [to_np(x["merged"]) for x in o]
-        if launch == "persistent":
-            # graph replays, with eager work in between, give the same maps
-            o2 = [ps.alloc_outputs(camera_set=i) for i in range(3)]
-            ps.capture_graph(dev, o2)
-            for rep in range(3):
-                for x in o2:
-                    x["merged"]["depth"].fill_(-1.0)
-                ps.launch_graph()
-                torch.cuda.synchronize()
-                ps.run(dev, o)          # eager work between replays
-                torch.cuda.synchronize()
-                outs[f"graph{rep}"] = [to_np(x["merged"]) for x in o2]
+        # graph replays, with eager work in between, give the same maps (the
+        # grid launch's graph holds its per-job grids on two streams)
+        o2 = [ps.alloc_outputs(camera_set=i) for i in range(3)]
+        ps.capture_graph(dev, o2)
+        for rep in range(3):
+            for x in o2:
+                x["merged"]["depth"].fill_(-1.0)
+            ps.launch_graph()
+            torch.cuda.synchronize()
+            ps.run(dev, o)          # eager work between replays
+            torch.cuda.synchronize()
+            outs[f"{launch}_graph{rep}"] = [to_np(x["merged"]) for x in o2]
         ps.close()
-    for key in ("persistent", "graph0", "graph1", "graph2"):
+    for key in ("persistent", "grid_graph0", "grid_graph1", "grid_graph2", "persistent_graph0",
+                "persistent_graph1", "persistent_graph2"):
         for a, b in zip(outs["grid"], outs[key]):
             for name in a:
                 assert np.array_equal(a[name], b[name], equal_nan=True), (key, name)
