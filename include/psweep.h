@@ -235,7 +235,7 @@ psweep_status psweep_run_noalloc(psweep_ctx *ctx, const psweep_frame *frames, in
  * order, so it does not.  Its per-workgroup partial sums go to the context
  * workspace (the plane-chunk region of that soft run), so the call must be
  * ordered after the run and before the next run on the same workspace, like
- * every call on a context.  Windows 5, 7, 9 and up to three sources
+ * every call on a context.  Windows 5, 7, 9 and up to four sources
  * (EUNSUPPORTED otherwise). */
 psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_invdepth,
                                          float *const *d_grad_src, double *d_grad_pose, void *hip_stream);

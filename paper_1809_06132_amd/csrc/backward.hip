@@ -241,12 +241,15 @@ struct Backward {
                 if (lane == 0) theta_rng = hi - lo;
             }
             if (wave == 0) {
-                // probes: 3 x 3 sample positions of the tile at the chunk's
-                // first and last plane, 18 lanes per source
-                const int s = lane / 18, p = lane - 18 * (lane / 18), q = p % 9;
+                // probes: 3 x 3 sample positions of the tile (without the
+                // centre for four sources, so that they fit the wave) at the
+                // chunk's first and last plane: 2 NP lanes per source
+                constexpr int NP = S <= 3 ? 9 : 8;
+                const int s = lane / (2 * NP), p = lane - 2 * NP * (lane / (2 * NP));
+                const int q = (p % NP) + (NP == 8 && p % NP >= 4 ? 1 : 0);
                 float u = __builtin_nanf(""), v = __builtin_nanf("");
                 if (s < S && k_hi > k_lo) {
-                    const int k = p < 9 ? k_lo : k_hi - 1;
+                    const int k = p < NP ? k_lo : k_hi - 1;
                     const int pc = blockIdx.x * TXO + (q % 3) * (kWave / 2 - 1) + (q % 3) / 2;   // 0, 31, 63
                     const int pr = sr0 + (q / 3) * ((T - 1) / 2) + (q / 3) / 2 * ((T - 1) % 2);
                     const float px_ = ((float)pc - J.cx) * J.inv_fx, py_ = ((float)pr - J.cy) * J.inv_fy;
@@ -644,6 +647,7 @@ const void *psw_backward_kernel(int win, int n_src, int img, int image_grads) {
         if (n_src == 1) return (const void *)&psw::backward_kernel<W, 1, I, G>;         \
         if (n_src == 2) return (const void *)&psw::backward_kernel<W, 2, I, G>;         \
         if (n_src == 3) return (const void *)&psw::backward_kernel<W, 3, I, G>;         \
+        if (n_src == 4) return (const void *)&psw::backward_kernel<W, 4, I, G>;         \
     }
     PSW_B(5, 0, true) PSW_B(7, 0, true) PSW_B(9, 0, true) PSW_B(5, 1, true) PSW_B(7, 1, true) PSW_B(9, 1, true)
     PSW_B(5, 0, false) PSW_B(7, 0, false) PSW_B(9, 0, false) PSW_B(5, 1, false) PSW_B(7, 1, false)
@@ -663,6 +667,7 @@ size_t psw_backward_lds(int win, int n_src, int image_grads) {
         if (n_src == 1) return psw::Backward<W, 1, 0, G>::lds_bytes();       \
         if (n_src == 2) return psw::Backward<W, 2, 0, G>::lds_bytes();       \
         if (n_src == 3) return psw::Backward<W, 3, 0, G>::lds_bytes();       \
+        if (n_src == 4) return psw::Backward<W, 4, 0, G>::lds_bytes();       \
     }
     PSW_L(5, true) PSW_L(7, true) PSW_L(9, true) PSW_L(5, false) PSW_L(7, false) PSW_L(9, false)
 #undef PSW_L

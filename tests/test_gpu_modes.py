@@ -181,6 +181,8 @@ BWD_CASES = [
     # a variance floor below 1/16: the image-gradient taps skip the
     # fixed-point LDS patch and go to the gradient images directly
     (7, 2, 2, 80, 60, 12, 7, 0.05),
+    # four sources (one workgroup per CU: its patches fill the LDS)
+    (9, 4, 2, 80, 60, 8, 8, 1.0),
 ]
 
 
