@@ -97,6 +97,8 @@ def lib():
     L.or_soft_forward.restype = None
     L.or_soft_backward.argtypes = [PR, PC, PI, _i32, PC, PI, PP, _i32, _i32, _i32, _i32, _p, _p, _p]
     L.or_soft_backward.restype = None
+    L.or_soft_hypothesis.argtypes = [PR, PC, _i32, _i32, _i32]
+    L.or_soft_hypothesis.restype = _d
     L.or_filter.argtypes = [PC, _p, _i32, _i32, _p, _p, _p, _d, _d, _d, _d, _d, _i32, _p, _p]
     L.or_filter.restype = None
     L.or_threads.argtypes = []
@@ -372,6 +374,13 @@ def soft_argmin(costs, rhos, temperature):
     lib().or_soft_argmin(C.ctypes.data, r.ctypes.data, len(C), float(temperature), ctypes.byref(rh),
                          ctypes.byref(lse))
     return rh.value, lse.value
+
+
+def soft_hypothesis(level, settings, ref_cam, k: int, i: int, j: int) -> float:
+    """The soft-argmin's value of plane k at reference pixel (i, j): the
+    inverse z-depth of the point where the pixel's Eq. (1) ray meets the plane
+    (the parameter of a fronto plane)."""
+    return lib().or_soft_hypothesis(ctypes.byref(params(level, settings)), ctypes.byref(camera(ref_cam)), k, i, j)
 
 
 def soft_forward(level, settings, ref_cam, ref_img, src_cams, src_imgs, poses, pixels=None):

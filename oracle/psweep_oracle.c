@@ -488,12 +488,30 @@ void or_merge(const or_camera *full, const or_params *p0, const or_params *p1,
 }
 
 /* ------------------------------------------------------------------------ */
-/* soft-argmin over the fronto planes and its analytic gradient             */
+/* soft-argmin over the planes and its analytic gradient                   */
 /* ------------------------------------------------------------------------ */
 
 /*
+ * Hypothesis value of plane k at reference pixel (i, j) for the soft-argmin:
+ * the inverse z-depth of the point where the pixel's Eq. (1) ray meets the
+ * plane.  A fronto plane's is its parameter rho_k; along the unit ray r a
+ * ground plane n_g . X = d_g - h is met at range (d_g - h) / (n_g . r), so its
+ * value is (n_g . r) / ((d_g - h) r_z).  (The soft-argmin has no counterpart
+ * in the paper; the planes are the paper's.)
+ */
+double or_soft_hypothesis(const or_params *p, const or_camera *rc, int k, int i, int j)
+{
+    const double prm = or_plane_param(p, k, NULL);
+    if (k < p->n_fronto) return prm;
+    double r[3];
+    or_unproject(rc, i, j, r);
+    const double nr = p->ground_n[0] * r[0] + p->ground_n[1] * r[1] + p->ground_n[2] * r[2];
+    return nr / ((p->ground_d - prm) * r[2]);
+}
+
+/*
  * Soft-argmin of one pixel (no counterpart in the paper; the hypotheses are
- * the paper's fronto planes): with l_k = -C_k / T over the valid planes (C_k
+ * the paper's planes): with l_k = -C_k / T over the valid planes (C_k
  * not NaN), p = softmax(l) and rho_hat = sum_k p_k rho_k, lse = log sum_k
  * exp(l_k), both computed with the largest l_k taken out.  No valid plane:
  * rho_hat = NaN and lse = -inf.
@@ -519,7 +537,8 @@ void or_soft_argmin(const double *C, const double *rho, int32_t P, double T, dou
 }
 
 /*
- * Soft-argmin inverse depth of every pixel over the fronto planes' costs.
+ * Soft-argmin inverse depth of every pixel over the planes' costs, each plane
+ * standing for its hypothesis value at the pixel (or_soft_hypothesis).
  */
 void or_soft_forward(const or_params *p, const or_camera *rc, const or_image *ref, int32_t S,
                      const or_camera *scs, const or_image *srcs, const or_pose *poses,
@@ -533,7 +552,7 @@ void or_soft_forward(const or_params *p, const or_camera *rc, const or_image *re
         double *C = (double *)malloc(sizeof(double) * P);
         double *rho = (double *)malloc(sizeof(double) * P);
         pixel_costs(p, rc, ref, S, scs, srcs, poses, i, j, C, NULL, NULL);
-        for (int k = 0; k < P; ++k) rho[k] = or_plane_param(p, k, NULL);
+        for (int k = 0; k < P; ++k) rho[k] = or_soft_hypothesis(p, rc, k, i, j);
         or_soft_argmin(C, rho, P, p->temperature, &rho_hat[e], &lse[e]);
         free(rho);
         free(C);
@@ -576,13 +595,13 @@ void or_soft_backward(const or_params *p, const or_camera *rc, const or_image *r
             for (int k = 0; k < P; ++k) {
                 if (isnan(C[k])) continue;
                 double ex = exp(-C[k] / T - m);
-                se += ex; sr += ex * or_plane_param(p, k, NULL);
+                se += ex; sr += ex * or_soft_hypothesis(p, rc, k, i, j);
             }
             double rh = sr / se;
             for (int k = 0; k < P; ++k) {
                 if (isnan(C[k])) continue;
                 double pk = exp(-C[k] / T - m) / se;
-                double dC = gp * (-1.0 / T) * pk * (or_plane_param(p, k, NULL) - rh);
+                double dC = gp * (-1.0 / T) * pk * (or_soft_hypothesis(p, rc, k, i, j) - rh);
                 double cs[64];
                 int vs[64], chosen[64];
                 for (int s = 0; s < S; ++s) { cs[s] = Cs[(int64_t)k * S + s]; vs[s] = !isnan(cs[s]); }

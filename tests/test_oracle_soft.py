@@ -133,6 +133,61 @@ def test_image_gradient_matches_central_differences(frame):
     assert checked == 12
 
 
+GLEVEL = Level(n_fronto=8, near=1.0, far=15.0, n_ground=6, h_lo=-0.4, h_hi=0.4, window=5)
+GSET_FD = Settings(levels=[GLEVEL], best_k=2, mode="soft", temperature=0.1, var_floor=1e-6)
+
+
+def test_ground_hypothesis_is_the_inverse_depth_of_the_cut(frame):
+    """A ground plane's value at a pixel is 1 / z of the point where the
+    pixel's ray meets it: the oracle's own warp with an identity pose gives
+    that point; a fronto plane's value is its parameter."""
+    ident = Pose(np.eye(3), np.zeros(3))
+    cam = frame.ref_cam
+    checked = 0
+    for k in range(GLEVEL.n_fronto + GLEVEL.n_ground):
+        for (i, j) in ((5, 30), (24, 20), (40, 33), (10, 2)):
+            w = oracle.warp(GLEVEL, GSET_FD, cam, cam, ident, k, i, j)
+            rho = oracle.soft_hypothesis(GLEVEL, GSET_FD, cam, k, i, j)
+            if k < GLEVEL.n_fronto:
+                assert rho == pytest.approx(oracle.plane_param(GLEVEL, GSET_FD, k)[0], rel=1e-15)
+            if w is None:
+                continue
+            assert rho == pytest.approx(1.0 / w[2][2], rel=1e-12), (k, i, j)
+            checked += 1
+    assert checked > 20
+
+
+@pytest.mark.parametrize("eps,tol", [(1e-4, 2e-3)])
+def test_pose_gradient_with_ground_planes_matches_central_differences(smooth_frame, eps, tol):
+    """Fronto and ground planes together: each plane stands for its
+    per-pixel inverse depth, in the forward and in the gradient alike."""
+    fr = smooth_frame
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=(RECT[3], RECT[2]))
+    _, gp = oracle.soft_backward(GLEVEL, GSET_FD, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses, RECT, g)
+    x0, y0, w, h = RECT
+    ys, xs = np.mgrid[y0:y0 + h, x0:x0 + w]
+    pix = np.stack([xs.ravel(), ys.ravel()], 1)
+
+    def loss(poses):
+        rh, _ = oracle.soft_forward(GLEVEL, GSET_FD, fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, poses, pixels=pix)
+        return float((np.where(np.isnan(rh), 0.0, rh) * g.ravel()).sum())
+
+    fd = np.zeros_like(gp)
+    for s_ in range(2):
+        for a in range(6):
+            xi = np.zeros(6)
+            xi[a] = eps
+            pp = list(fr.poses)
+            pp[s_] = _perturbed(fr.poses[s_], xi)
+            lp = loss(pp)
+            pp[s_] = _perturbed(fr.poses[s_], -xi)
+            fd[s_, a] = (lp - loss(pp)) / (2 * eps)
+    rel = np.linalg.norm(fd - gp) / np.linalg.norm(fd)
+    assert np.linalg.norm(fd) > 0
+    assert rel < tol, (rel, fd, gp)
+
+
 def test_soft_argmin_golden():
     """The soft-argmin step against the hand-computed closed-form values of
     tests/golden/soft_argmin_hand.txt: a wrong temperature scale (exp(-C/2T)),
