@@ -18,8 +18,9 @@
  *   - two resolution levels: a downsampled full field of view and a
  *     full-resolution centre crop, fused into one full-resolution map (Sec.
  *     III-A, multi-scale strategy);
- *   - optionally a soft-argmin over the fronto planes with a gradient with
- *     respect to the source images and the source poses.
+ *   - optionally a soft-argmin over the planes (each standing for the
+ *     inverse z-depth at which the pixel's ray meets it) with a gradient
+ *     with respect to the source images and the source poses.
  *
  * Conventions shared by every call:
  *   - Pixel (i, j) has its centre at (u, v) = (i, j); normalized coordinates
@@ -150,7 +151,8 @@ typedef struct {
 typedef struct {
     psweep_maps merged;                       /* full reference resolution */
     psweep_maps level[PSWEEP_MAX_LEVELS];     /* per level, at the level's size (optional) */
-    float *soft_invdepth;                     /* soft mode, full resolution */
+    float *soft_invdepth;                     /* soft mode, full resolution: sum_k p_k rho_k, rho_k the
+                                                 inverse z-depth of the pixel's ray at plane k */
     float *soft_lse;                          /* soft mode: log-sum-exp of -cost / T */
     int64_t soft_pitch;
     /* Optional (NULL = not written), winner-take-all mode with the grid
@@ -168,8 +170,9 @@ typedef struct {
 /* Create a context for `cfg`.  EINVAL on inconsistent settings (even window,
  * fewer than 2 planes in a used family, non-positive plane distances, sizes
  * or counts out of range, best_k outside [1, max_sources], unknown
- * image_format); EUNSUPPORTED for soft mode with ground planes, with two
- * levels, with a downsampled or cropped level or with the persistent launch,
+ * image_format); EUNSUPPORTED for soft mode with two levels, with a
+ * downsampled or cropped level, with FP16/BF16 staging or with the
+ * persistent launch,
  * and for float images with anything but one full-resolution level on the
  * grid launch.  *out receives the context. */
 psweep_status psweep_create(const psweep_config *cfg, psweep_ctx **out);
@@ -228,8 +231,9 @@ psweep_status psweep_run_noalloc(psweep_ctx *ctx, const psweep_frame *frames, in
  * and its atomics) and to every source pose as a left perturbation X_src ->
  * X_src + v + omega x X_src (d_grad_pose: device doubles [n_src][6] ordered
  * v, omega; overwritten).  Uses the images and soft outputs of the last
- * psweep_run, which must have been a soft run (ESTATE otherwise).  Warps are
- * recomputed, not stored.  The planes are split into chunks swept by separate
+ * psweep_run, which must have been a soft run (ESTATE otherwise).  Both
+ * plane families take part, as in the forward.  Warps are recomputed, not
+ * stored.  The planes are split into chunks swept by separate
  * workgroups.  Image gradients are accumulated with atomics, so they vary in
  * the last bits from run to run.  The pose gradient is summed in a fixed
  * order, so it does not.  Its per-workgroup partial sums go to the context

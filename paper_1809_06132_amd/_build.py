@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libpsweep.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "misc_kernels.hip", "backward.hip", "inst_grid.hip", "inst_grid8.hip", "inst_extra.hip", "inst_small.hip",
+SOURCES = ["api.cpp", "misc_kernels.hip", "backward.hip", "backward_ground.hip", "inst_grid.hip", "inst_grid8.hip", "inst_extra.hip", "inst_small.hip",
            "inst_persistent.hip", "inst_f32img.hip", "tsdf.hip", "tsdf_api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

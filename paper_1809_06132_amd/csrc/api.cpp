@@ -25,7 +25,7 @@ extern "C" const void *psw_merge_kernel();
 extern "C" const void *psw_chunk_merge_kernel();
 extern "C" const void *psw_filter_kernel();
 extern "C" const void *psw_mask_kernel();
-extern "C" const void *psw_backward_kernel(int win, int n_src, int img, int image_grads);
+extern "C" const void *psw_backward_kernel(int win, int n_src, int img, int image_grads, int ground);
 extern "C" size_t psw_backward_lds(int win, int n_src, int image_grads);
 extern "C" int psw_backward_tile_rows();
 extern "C" int psw_backward_threads(int image_grads);
@@ -233,7 +233,6 @@ psweep_status check_config(const psweep_config *c) {
     }
     if (c->mode == PSWEEP_MODE_SOFT) {
         if (!single_full(*c)) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode needs one full-resolution level");
-        if (c->level[0].n_ground != 0) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode sweeps fronto planes only");
         if (c->launch != PSWEEP_LAUNCH_GRID) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode uses the grid launch");
         if (c->storage != PSWEEP_STORAGE_F32) return fail(nullptr, PSWEEP_EUNSUPPORTED, "soft mode stages in FP32");
         if (!(c->temperature > 0.0)) return bad("temperature must be > 0");
@@ -1194,7 +1193,8 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     const int win = ctx->cfg.level[0].window;
     bool any_image = false;
     for (int s = 0; s < C.n_src; ++s) any_image |= gsrc[s] != nullptr;
-    const void *bk = psw_backward_kernel(win, C.n_src, ctx->cfg.image_format, any_image ? 1 : 0);
+    const void *bk = psw_backward_kernel(win, C.n_src, ctx->cfg.image_format, any_image ? 1 : 0,
+                                         ctx->cfg.level[0].n_ground > 0 ? 1 : 0);
     if (!bk) return fail(ctx, PSWEEP_EUNSUPPORTED, "no backward kernel for this window / source count");
     const size_t lds = psw_backward_lds(win, C.n_src, any_image ? 1 : 0);
     if (lds > 65536) PSW_HIP(hipFuncSetAttribute(bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds), "lds limit");
@@ -1209,7 +1209,7 @@ psweep_status psweep_soft_depth_backward(psweep_ctx *ctx, const float *d_grad_in
     // SIMD, at least two planes per chunk.  Fewer, longer chunks repeat less
     // of the per-tile set-up and share each image-gradient patch over more
     // planes (C4: 0.56 ms with 6 chunks, 0.58 ms with 10, 0.61 ms with 16)
-    const int nf = ctx->cfg.level[0].n_fronto;
+    const int nf = ctx->cfg.level[0].n_fronto + ctx->cfg.level[0].n_ground;   // every plane
     const long long wpg = psw_backward_threads(any_image ? 1 : 0) / kWave;   // waves per workgroup
     int nch = tiles ? (int)((14LL * ctx->n_cu * 4 + wpg * tiles - 1) / (wpg * tiles)) : 1;
     nch = std::max(1, std::min(std::min(nch, 16), std::max(1, nf / 2)));

@@ -538,12 +538,17 @@ struct Tile {
             // still warps its share of the tile's rows for the others, unless
             // no wave of the tile is live, when the tile skips the family.
             bool live = false;
+            // soft mode, ground planes: a plane's value at an output pixel is
+            // the inverse z-depth of the ray's cut, (n . r) / ((d - h) r_z) =
+            // gfac / (d - h) with gfac = (n . (x, y, tau)) / tau
+            float gfac[SOFT ? R : 1];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const float yo = ((float)(or0 + i) - J.cy) * J.inv_fy;
                 const float t = ray_tau(x, yo, xi, nullptr);
                 const float g = fam ? fmaf(J.gn[0], x, fmaf(J.gn[1], yo, J.gn[2] * t)) : t;
                 live |= ((ref_ok >> i) & 1u) && g > 0.0f;
+                if constexpr (SOFT) gfac[i] = fam ? g / t : 1.0f;
             }
             const bool wave_live = __builtin_amdgcn_ballot_w64(live) != 0;
             if (!__syncthreads_or(wave_live)) continue;
@@ -599,6 +604,9 @@ struct Tile {
             __syncthreads();
             for (int kk = 0; kk < np; ++kk) {
                 const int k = k0 + kk;
+                // soft mode: plane k's value at a pixel is gfac * pf, pf = theta_k
+                // (fronto, gfac = 1) or 1 / (d - h_k) (ground) (wave-uniform)
+                const float pf = !SOFT ? 0.0f : fam ? 1.0f / (J.gd - cptr(J.theta)[k]) : cptr(J.theta)[k];
                 const ST *cur = tile + (size_t)(kk & 1) * S * T * kWave;
                 if (kk + 1 < np) warp_plane(k + 1, tile + (size_t)((kk + 1) & 1) * S * T * kWave);
                 if (wave_live) {
@@ -703,7 +711,7 @@ struct Tile {
                             const float l = -C * invT;
                             const float nm = fmaxf(c1[i], l);
                             const float ea = __expf(c1[i] - nm), eb = __expf(l - nm);
-                            const float th = cptr(J.theta)[k];
+                            const float th = gfac[i] * pf;
                             c2[i] = fmaf(c2[i], ea, eb);
                             cm[i] = fmaf(cm[i], ea, eb * th);
                             c1[i] = nm;

@@ -23,7 +23,7 @@ const void *psw_merge_kernel() { return nullptr; }
 const void *psw_chunk_merge_kernel() { return nullptr; }
 const void *psw_filter_kernel() { return nullptr; }
 const void *psw_mask_kernel() { return nullptr; }
-const void *psw_backward_kernel(int, int, int, int) { return nullptr; }
+const void *psw_backward_kernel(int, int, int, int, int) { return nullptr; }
 size_t psw_backward_lds(int, int, int) { return 0; }
 int psw_backward_tile_rows() { return 4; }
 int psw_backward_threads(int) { return 512; }

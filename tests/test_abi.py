@@ -64,7 +64,7 @@ def _cfg(psweep, **kw):
     ({"n_levels": 3}, -1),
     ({"storage": 7}, -1),
     ({"0.n_ground": 4, "0.h_lo": -0.5, "0.h_hi": 0.5, "ground_d": 0.2}, -1),  # planes above the camera
-    ({"mode": 1, "0.n_ground": 4, "0.h_lo": -0.5, "0.h_hi": 0.5}, -5),      # soft with ground planes
+    ({"mode": 1, "storage": 1}, -5),                                         # soft mode stages in FP32
     ({"mode": 1, "launch": 1}, -5),
     ({"launch": 1, "0.window": 5}, -5),
     ({"0.crop_w": 100, "0.crop_h": 100}, -5),

@@ -147,16 +147,19 @@ def test_persistent_and_graph_match_grid(storage, n_src, ptile):
 # ---------------------------------------------------------------------------
 # soft-argmin forward and backward
 # ---------------------------------------------------------------------------
-def _soft_case():
+def _soft_case(n_ground=0):
     fr = scenegen.random_small_frame(w=64, h=48, n_src=2, seed=4, f=40.0)
-    lv = Level(n_fronto=16, near=1.0, far=15.0, window=5)
+    lv = Level(n_fronto=16, near=1.0, far=15.0, window=5, n_ground=n_ground, h_lo=-0.4, h_hi=0.4)
     st = Settings(levels=[lv], best_k=2, mode="soft", temperature=0.1, var_floor=1.0)
     return fr, lv, st
 
 
-def test_soft_forward_matches_oracle():
+@pytest.mark.parametrize("n_ground", [0, 8])
+def test_soft_forward_matches_oracle(n_ground):
+    """rho_hat against the oracle, fronto planes alone and with ground
+    planes (each standing for the inverse z-depth of the pixel's ray at it)."""
     PlaneSweep, frame_to_device = _gpu()
-    fr, lv, st = _soft_case()
+    fr, lv, st = _soft_case(n_ground)
     ps = PlaneSweep(st, 64, 48, 2)
     ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
     out = ps.alloc_outputs()
@@ -168,14 +171,21 @@ def test_soft_forward_matches_oracle():
     ok = np.isfinite(rho)
     assert ok.sum() > 500
     assert np.array_equal(ok, np.isfinite(rh))
-    rel = np.abs(rh[ok] - rho[ok]) / rho[ok]
+    rel = np.abs(rh[ok] - rho[ok]) / np.maximum(np.abs(rho[ok]), 1e-2)
+    if n_ground:
+        # the ground planes take part: rho_hat differs from the fronto-only one
+        rho_f, _ = oracle.soft_forward(*_soft_case(0)[1:], fr.ref_cam, fr.ref, fr.src_cams, fr.srcs, fr.poses)
+        both = ok & np.isfinite(rho_f)
+        assert (np.abs(rho_f[both] - rho[both]) > 1e-3 * np.abs(rho[both])).mean() > 0.2
     print("soft rho rel err max", rel.max(), "p99.9", np.quantile(rel, 0.999))
     assert np.quantile(rel, 0.999) <= 1e-4 and rel.max() <= 1e-3
 
 
 BWD_CASES = [
-    # (window, n_src, best_k, w, h, n_fronto, seed, var_floor)
+    # (window, n_src, best_k, w, h, n_fronto, seed, var_floor[, n_ground])
     (5, 2, 2, 64, 48, 16, 4, 1.0),
+    # fronto and ground planes
+    (7, 2, 2, 80, 60, 10, 9, 1.0, 8),
     (7, 3, 2, 90, 70, 12, 5, 1.0),
     (9, 1, 1, 100, 60, 10, 6, 1.0),
     # a variance floor below 1/16: the image-gradient taps skip the
@@ -186,7 +196,8 @@ BWD_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"w{c[0]}_S{c[1]}_K{c[2]}_{c[3]}x{c[4]}_vf{c[7]}")
+@pytest.mark.parametrize("case", BWD_CASES,
+                         ids=lambda c: f"w{c[0]}_S{c[1]}_K{c[2]}_{c[3]}x{c[4]}_vf{c[7]}_g{c[8] if len(c) > 8 else 0}")
 def test_soft_backward_matches_oracle_gradient(case):
     """The GPU gradient of sum(g * rho_hat) against the oracle's FP64
     analytic gradient (itself pinned by central differences), for a dense
@@ -194,9 +205,10 @@ def test_soft_backward_matches_oracle_gradient(case):
     on a temporary device copy of the frame, followed by allocations: the
     wrapper holds the reference image that the backward reads again."""
     PlaneSweep, frame_to_device = _gpu()
-    win, S, K, W, H, nf, seed, vfloor = case
+    win, S, K, W, H, nf, seed, vfloor = case[:8]
+    ng = case[8] if len(case) > 8 else 0
     fr = scenegen.random_small_frame(w=W, h=H, n_src=S, seed=seed, f=0.62 * W)
-    lv = Level(n_fronto=nf, near=1.0, far=15.0, window=win)
+    lv = Level(n_fronto=nf, near=1.0, far=15.0, window=win, n_ground=ng, h_lo=-0.4, h_hi=0.4)
     st = Settings(levels=[lv], best_k=K, mode="soft", temperature=0.1, var_floor=vfloor)
     ps = PlaneSweep(st, W, H, S)
     ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
@@ -222,11 +234,12 @@ def test_soft_backward_matches_oracle_gradient(case):
     assert rel_pose <= 1e-3 and rel_img <= 1e-3
 
 
-def test_soft_backward_pose_only_matches_full():
+@pytest.mark.parametrize("n_ground", [0, 8])
+def test_soft_backward_pose_only_matches_full(n_ground):
     """Skipping the image gradients (NULL source-gradient pointers) leaves the
-    pose gradient unchanged."""
+    pose gradient unchanged, with fronto planes alone and with ground planes."""
     PlaneSweep, frame_to_device = _gpu()
-    fr, lv, st = _soft_case()
+    fr, lv, st = _soft_case(n_ground)
     ps = PlaneSweep(st, 64, 48, 2)
     ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
     out = ps.alloc_outputs()
