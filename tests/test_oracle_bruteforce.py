@@ -124,8 +124,8 @@ def _compare(frame, level, st):
             c = filled[j, i]
             srt = np.sort(np.delete(c, k))
             assert abs(res["cost1"][j, i] - c[k]) < 1e-12
-            assert abs(res["cost2"][j, i] - (srt[0] if srt.size else np.inf)) < 1e-12 or \
-                (np.isinf(srt[0]) and np.isinf(res["cost2"][j, i]))
+            want2, got2 = (srt[0] if srt.size else np.inf), res["cost2"][j, i]
+            assert (np.isinf(want2) and np.isinf(got2)) or abs(got2 - want2) < 1e-12
             lo, hi = (0, F - 1) if k < F else (F, P - 1)
             delta = 0.0
             if lo <= k - 1 and k + 1 <= hi and np.isfinite(c[k - 1]) and np.isfinite(c[k + 1]):
