@@ -89,11 +89,14 @@ def test_integer_valued_float_images_match_u8_path():
     assert np.abs(a["cost1"][both] - b["cost1"][both]).max() <= 1e-5
 
 
-def test_float_images_soft_forward_and_backward():
+@pytest.mark.parametrize("n_ground", [0, 6])
+def test_float_images_soft_forward_and_backward(n_ground):
+    """Soft forward and backward on float images, with fronto planes alone
+    and with ground planes beside them."""
     PlaneSweep = _gpu()
     W, H, S = 64, 48, 2
     fr = _float_frame(scenegen.random_small_frame(w=W, h=H, n_src=S, seed=4, f=40.0), 5)
-    lv = Level(n_fronto=16, near=1.0, far=15.0, window=5)
+    lv = Level(n_fronto=16, near=1.0, far=15.0, window=5, n_ground=n_ground, h_lo=-0.4, h_hi=0.4)
     st = Settings(levels=[lv], best_k=2, mode="soft", temperature=0.1, var_floor=1.0)
     ps = PlaneSweep(st, W, H, S, image_format="f32")
     ps.set_cameras(0, fr.ref_cam, fr.src_cams, fr.poses)
@@ -117,18 +120,20 @@ def test_float_images_soft_forward_and_backward():
                                     (x0, y0, w, h), g[y0:y0 + h, x0:x0 + w])
     rel_pose = np.linalg.norm(gp - ogp) / np.linalg.norm(ogp)
     rel_img = np.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(gs, ogs)) / sum(np.sum(b ** 2) for b in ogs))
-    print("float images: pose rel", rel_pose, "img rel", rel_img)
+    print("float images, ground planes", n_ground, ": pose rel", rel_pose, "img rel", rel_img)
     assert rel_pose <= 1e-3 and rel_img <= 1e-3
 
 
-def test_autograd_float_sources_get_exact_gradients():
+@pytest.mark.parametrize("n_ground", [0, 6])
+def test_autograd_float_sources_get_exact_gradients(n_ground):
     """Through torch.autograd: float sources of an f32-image sweep receive the
-    library's backward gradient, and the pose gradient matches it too."""
+    library's backward gradient, and the pose gradient matches it too (fronto
+    planes alone, and with ground planes)."""
     _gpu()
     from paper_1809_06132_amd.autograd import SoftDepthSweep
     W, H, S = 64, 48, 2
     fr = _float_frame(scenegen.random_small_frame(w=W, h=H, n_src=S, seed=4, f=40.0), 6)
-    lv = Level(n_fronto=16, near=1.0, far=15.0, window=5)
+    lv = Level(n_fronto=16, near=1.0, far=15.0, window=5, n_ground=n_ground, h_lo=-0.4, h_hi=0.4)
     st = Settings(levels=[lv], best_k=2, mode="soft", temperature=0.1, var_floor=1.0)
     sw = SoftDepthSweep(st, fr.ref_cam, fr.src_cams, fr.poses, image_format="f32")
     d = _dev(fr)
