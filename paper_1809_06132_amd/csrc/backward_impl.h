@@ -118,6 +118,16 @@ struct Backward {
     static constexpr size_t lds_bytes() {
         return lds_tile() + (size_t)(NCH * S + 1) * TYO * kWave * 4 + lds_patch();
     }
+    // Occupancy hint: the pose-only form of one or two sources leaves LDS for
+    // three workgroups per CU (6 waves per SIMD), which its registers reach
+    // when held to 80 (a few spills outside the hottest loops; C4's pose-only
+    // backward 0.40 -> 0.36 ms).  Elsewhere LDS holds the CU to two
+    // workgroups, and the hint would only add spills (1: no hint); so would it
+    // in the ground form, whose per-row values of both families need about
+    // 100 registers.
+    static constexpr int waves_per_eu() {
+        return !GI && !GND && 3 * (lds_bytes() + 1024) <= 160 * 1024 ? 6 : 1;
+    }
 
     __device__ static void run(const JobDev *__restrict__ Jp, const float *__restrict__ gin,
                                const float *__restrict__ rho_hat, const float *__restrict__ lse, int64_t spitch,
@@ -666,7 +676,8 @@ struct Backward {
 };
 
 template <int WIN, int S, int IMG, bool GI, bool GND>
-__global__ __launch_bounds__((Backward<WIN, S, IMG, GI, GND>::NW * kWave)) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
+__global__ __launch_bounds__((Backward<WIN, S, IMG, GI, GND>::NW * kWave))
+__attribute__((amdgpu_waves_per_eu(Backward<WIN, S, IMG, GI, GND>::waves_per_eu()))) void backward_kernel(const JobDev *__restrict__ job, const float *__restrict__ gin,
                                                         const float *__restrict__ rho, const float *__restrict__ lse,
                                                         int64_t spitch, float *g0, float *g1, float *g2, float *g3,
                                                         double *gpart) {
