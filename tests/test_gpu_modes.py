@@ -193,6 +193,9 @@ BWD_CASES = [
     (7, 2, 2, 80, 60, 12, 7, 0.05),
     # four sources (one workgroup per CU: its patches fill the LDS)
     (9, 4, 2, 80, 60, 8, 8, 1.0),
+    # ground planes with three and with four sources
+    (5, 3, 2, 90, 70, 10, 10, 1.0, 6),
+    (9, 4, 2, 80, 60, 8, 11, 1.0, 6),
 ]
 
 
