@@ -214,10 +214,16 @@ struct Texel;
 template <>
 struct Texel<0> {
     static constexpr uint32_t bytes = 8;
-    __device__ static float sample(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be) {
-        const auto q = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+    typedef unsigned int Raw __attribute__((ext_vector_type(2)));
+    __device__ static Raw raw(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+        return __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+    }
+    __device__ static float blend(Raw q, float al, float be) {
         const float t = fmaf(al, half_hi(q[1]), half_lo(q[1]));
         return fmaf(al, half_hi(q[0]), fmaf(be, t, half_lo(q[0])));
+    }
+    __device__ static float sample(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be) {
+        return blend(raw(rs, off), al, be);
     }
     __device__ static void slope(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be, float *du, float *dv) {
         const auto q = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
@@ -230,15 +236,22 @@ template <>
 struct Texel<1> {
     static constexpr uint32_t bytes = 16;
     struct Quad { float p00, p10, p01, p11; };
+    typedef unsigned int Raw __attribute__((ext_vector_type(4)));
+    __device__ static Raw raw(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+        return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    }
     __device__ static Quad load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        const Raw q = raw(rs, off);
         return {__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3])};
     }
-    __device__ static float sample(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be) {
-        const Quad q = load(rs, off);
+    __device__ static float blend(Raw r, float al, float be) {
+        const Quad q = {__uint_as_float(r[0]), __uint_as_float(r[1]), __uint_as_float(r[2]), __uint_as_float(r[3])};
         const float top = fmaf(al, q.p10 - q.p00, q.p00);
         const float bot = fmaf(al, q.p11 - q.p01, q.p01);
         return fmaf(be, bot - top, top - 128.0f);
+    }
+    __device__ static float sample(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be) {
+        return blend(raw(rs, off), al, be);
     }
     __device__ static void slope(__amdgpu_buffer_rsrc_t rs, uint32_t off, float al, float be, float *du, float *dv) {
         const Quad q = load(rs, off);
@@ -576,27 +589,43 @@ struct Tile {
                         (void *)J.src[s].tex, (short)0, (int)(row_bytes * (uint32_t)J.src[s].h), 0x00020000);
                     const float px = h1x * x, py = h1y * x, pz = h1z * x;
                     ST *dst = buf + (size_t)s * T * kWave + lane;
+                    // two samples at a time: both texel loads are issued before
+                    // either is blended
 #pragma unroll
-                    for (int i = 0; i < NWR; ++i) {
-                        const int j = wave + NW * i;
-                        if (i == NWR - 1 && j >= T) break;
-                        const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
-                        const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
-                        const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
-                        const float m = __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z)));
-                        const float den = fmaf(sxi, m, Z);
-                        const float inv = __builtin_amdgcn_rcpf(den);
-                        const float u = fmaf(X * inv, sfx, scx);
-                        const float v = fmaf(Y * inv, sfy, scy);
-                        // 0 <= u <= wm1 as one unsigned compare of the bit patterns
-                        // (non-negative floats order like their bits; negative
-                        // values and NaN compare above wm1; u is never -0 here)
-                        const bool ok = (den > 0.0f) & (__float_as_uint(u) <= __float_as_uint(wm1)) &
-                                        (__float_as_uint(v) <= __float_as_uint(hm1));
-                        const uint32_t off = __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
-                        const float al = __builtin_amdgcn_fractf(u), be = __builtin_amdgcn_fractf(v);
-                        const float b = Texel<IMG>::sample(rs, off, al, be);
-                        dst[(size_t)j * kWave] = ok ? St::put(b) : St::bad();
+                    for (int i0 = 0; i0 < NWR; i0 += 2) {
+                        float al[2], be[2];
+                        bool ok[2], have[2];
+                        typename Texel<IMG>::Raw q[2];
+#pragma unroll
+                        for (int d = 0; d < 2; ++d) {
+                            const int i = i0 + d;
+                            have[d] = i < NWR && !(i == NWR - 1 && wave + NW * i >= T);
+                            if (!have[d]) continue;
+                            const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
+                            const float Y = fmaf(h3y, tf[i], fmaf(h2y, yw[i], py));
+                            const float Z = fmaf(h3z, tf[i], fmaf(h2z, yw[i], pz));
+                            const float m = __builtin_amdgcn_sqrtf(fmaf(X, X, fmaf(Y, Y, Z * Z)));
+                            const float den = fmaf(sxi, m, Z);
+                            const float inv = __builtin_amdgcn_rcpf(den);
+                            const float u = fmaf(X * inv, sfx, scx);
+                            const float v = fmaf(Y * inv, sfy, scy);
+                            // 0 <= u <= wm1 as one unsigned compare of the bit patterns
+                            // (non-negative floats order like their bits; negative
+                            // values and NaN compare above wm1; u is never -0 here)
+                            ok[d] = (den > 0.0f) & (__float_as_uint(u) <= __float_as_uint(wm1)) &
+                                    (__float_as_uint(v) <= __float_as_uint(hm1));
+                            const uint32_t off =
+                                __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
+                            al[d] = __builtin_amdgcn_fractf(u);
+                            be[d] = __builtin_amdgcn_fractf(v);
+                            q[d] = Texel<IMG>::raw(rs, off);
+                        }
+#pragma unroll
+                        for (int d = 0; d < 2; ++d) {
+                            if (!have[d]) continue;
+                            const float b = Texel<IMG>::blend(q[d], al[d], be[d]);
+                            dst[(size_t)(wave + NW * (i0 + d)) * kWave] = ok[d] ? St::put(b) : St::bad();
+                        }
                     }
                 }
             };
