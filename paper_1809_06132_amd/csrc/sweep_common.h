@@ -393,6 +393,11 @@ struct Tile {
     static constexpr int TYO = NW * R;               // output rows per tile
     static constexpr int T = TYO + 2 * HW;           // sample rows per tile
     static constexpr int NWR = (T + NW - 1) / NW;    // warp rows per wave
+    // rows whose texel loads the warp issues together: all of them where the
+    // registers they hold (two per load in flight) keep the occupancy that
+    // LDS allows (three or four sources, 8-bit images, FP32 staging, windows
+    // up to 9), else two
+    static constexpr int LG = (IMG == 0 && STORE == 0 && S >= 3 && R == 4 && WIN <= 9) ? NWR : 2;
     static constexpr int VR = R + 2 * HW;            // rows each wave runs down
     using St = Stage<STORE>;
     using ST = typename St::T;
@@ -589,16 +594,18 @@ struct Tile {
                         (void *)J.src[s].tex, (short)0, (int)(row_bytes * (uint32_t)J.src[s].h), 0x00020000);
                     const float px = h1x * x, py = h1y * x, pz = h1z * x;
                     ST *dst = buf + (size_t)s * T * kWave + lane;
-                    // two samples at a time: both texel loads are issued before
-                    // either is blended
+                    // the texel loads of LG rows are issued before the first of
+                    // them is blended, so that they overlap instead of each
+                    // waiting in turn
 #pragma unroll
-                    for (int i0 = 0; i0 < NWR; i0 += 2) {
-                        float al[2], be[2];
-                        bool ok[2], have[2];
-                        typename Texel<IMG>::Raw q[2];
+                    for (int i0 = 0; i0 < NWR; i0 += LG) {
+                        float al[LG], be[LG];
+                        bool ok[LG], have[LG];
+                        typename Texel<IMG>::Raw q[LG];
 #pragma unroll
-                        for (int d = 0; d < 2; ++d) {
+                        for (int d = 0; d < LG; ++d) {
                             const int i = i0 + d;
+                            // the last row may be past the tile
                             have[d] = i < NWR && !(i == NWR - 1 && wave + NW * i >= T);
                             if (!have[d]) continue;
                             const float X = fmaf(h3x, tf[i], fmaf(h2x, yw[i], px));
@@ -621,7 +628,7 @@ struct Tile {
                             q[d] = Texel<IMG>::raw(rs, off);
                         }
 #pragma unroll
-                        for (int d = 0; d < 2; ++d) {
+                        for (int d = 0; d < LG; ++d) {
                             if (!have[d]) continue;
                             const float b = Texel<IMG>::blend(q[d], al[d], be[d]);
                             dst[(size_t)(wave + NW * (i0 + d)) * kWave] = ok[d] ? St::put(b) : St::bad();
