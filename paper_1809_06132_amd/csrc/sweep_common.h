@@ -206,6 +206,15 @@ __device__ __forceinline__ double wsum_d(double v, const Shifts &sh) {
 // b = c0 + al c1 + be (c2 + al c3), three mixed-precision FMAs with FP32
 // rounding; IMG 1: four floats p00, p10, p01, p11.  Reads outside the buffer
 // return 0.
+// Indexed buffer loads (the buffer's stride in the resource, the element
+// index in a register): address = base + index * stride.  An index at or past
+// the resource's record count reads 0.
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
+__device__ U32x2 buffer_load_index_b64(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+__device__ U32x4 buffer_load_index_b128(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
 struct Half2 { _Float16 lo, hi; };
 __device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(Half2, w).lo; }
 __device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(Half2, w).hi; }
@@ -217,6 +226,10 @@ struct Texel<0> {
     typedef unsigned int Raw __attribute__((ext_vector_type(2)));
     __device__ static Raw raw(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
         return __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+    }
+    // texel `index` of a resource whose stride is `bytes`
+    __device__ static Raw at(__amdgpu_buffer_rsrc_t rs, uint32_t index) {
+        return buffer_load_index_b64(rs, (int)index, 0, 0, 0);
     }
     __device__ static float blend(Raw q, float al, float be) {
         const float t = fmaf(al, half_hi(q[1]), half_lo(q[1]));
@@ -239,6 +252,10 @@ struct Texel<1> {
     typedef unsigned int Raw __attribute__((ext_vector_type(4)));
     __device__ static Raw raw(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
         return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    }
+    // texel `index` of a resource whose stride is `bytes`
+    __device__ static Raw at(__amdgpu_buffer_rsrc_t rs, uint32_t index) {
+        return buffer_load_index_b128(rs, (int)index, 0, 0, 0);
     }
     __device__ static Quad load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
         const Raw q = raw(rs, off);
@@ -398,6 +415,11 @@ struct Tile {
     // LDS allows (three or four sources, 8-bit images, FP32 staging, windows
     // up to 9), else two
     static constexpr int LG = (IMG == 0 && STORE == 0 && S >= 3 && R == 4 && WIN <= 9) ? NWR : 2;
+    // texel loads by index into a texel-strided resource (no address shift,
+    // one instruction per sample less), except for the one tile that it takes
+    // past 128 VGPRs (two sources, window 9, 8-bit images, FP32 staging on the
+    // default tile: 129, i.e. three waves per SIMD), which keeps byte offsets
+    static constexpr bool kIndexed = !(IMG == 0 && STORE == 0 && S == 2 && WIN == 9 && R == 4 && NW == 4);
     static constexpr int VR = R + 2 * HW;            // rows each wave runs down
     using St = Stage<STORE>;
     using ST = typename St::T;
@@ -587,11 +609,14 @@ struct Tile {
                     const float sxi = J.src[s].xi, sfx = J.src[s].fx, sfy = J.src[s].fy;
                     const float scx = J.src[s].cx, scy = J.src[s].cy;
                     const float wm1 = J.src[s].wm1, hm1 = J.src[s].hm1;
-                    const uint32_t row_bytes = (uint32_t)J.src[s].w * Texel<IMG>::bytes;
-                    // buffer reads outside the texture return 0, so even the
-                    // address of an invalid sample cannot fault
+                    const uint32_t sw = (uint32_t)J.src[s].w;
+                    const uint32_t row_bytes = sw * Texel<IMG>::bytes;
+                    // the texture as an array of texels (stride Texel::bytes,
+                    // w h records), or as bytes: reads past it return 0, so
+                    // even the address of an invalid sample cannot fault
                     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                        (void *)J.src[s].tex, (short)0, (int)(row_bytes * (uint32_t)J.src[s].h), 0x00020000);
+                        (void *)J.src[s].tex, (short)(kIndexed ? Texel<IMG>::bytes : 0),
+                        (int)(kIndexed ? sw * (uint32_t)J.src[s].h : row_bytes * (uint32_t)J.src[s].h), 0x00020000);
                     const float px = h1x * x, py = h1y * x, pz = h1z * x;
                     ST *dst = buf + (size_t)s * T * kWave + lane;
                     // the texel loads of LG rows are issued before the first of
@@ -621,11 +646,13 @@ struct Tile {
                             // values and NaN compare above wm1; u is never -0 here)
                             ok[d] = (den > 0.0f) & (__float_as_uint(u) <= __float_as_uint(wm1)) &
                                     (__float_as_uint(v) <= __float_as_uint(hm1));
-                            const uint32_t off =
-                                __umul24((uint32_t)(int)v, row_bytes) + (uint32_t)(int)u * Texel<IMG>::bytes;
                             al[d] = __builtin_amdgcn_fractf(u);
                             be[d] = __builtin_amdgcn_fractf(v);
-                            q[d] = Texel<IMG>::raw(rs, off);
+                            if constexpr (kIndexed)
+                                q[d] = Texel<IMG>::at(rs, __umul24((uint32_t)(int)v, sw) + (uint32_t)(int)u);
+                            else
+                                q[d] = Texel<IMG>::raw(rs, __umul24((uint32_t)(int)v, row_bytes) +
+                                                               (uint32_t)(int)u * Texel<IMG>::bytes);
                         }
 #pragma unroll
                         for (int d = 0; d < LG; ++d) {
